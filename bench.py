@@ -1,0 +1,242 @@
+"""Benchmark of the fused collide-and-stream hot path on one MI355X.
+
+Default workload: D3Q19 BGK lid-driven cubic cavity on 256^3 cells (one-cell
+solid shell, lid moving at u = 0.1, Re = 1000 over the 254-cell cavity),
+FP32 shifted-population storage.  One "step" is one fused collide+stream
+update of the whole lattice (even and odd AA steps alternate) with the FP64
+domain reductions sampled every 100 steps (fused into the step).  Inputs are
+resident in HBM before timing starts.  The same run is repeated in FP64 and
+FP16 storage; their MLUPS, roofline fractions and the kinetic-energy /
+velocity error against the FP64 run are reported alongside.
+
+Prints ONE JSON line (rank 0).  Only one GPU is used: --gpus above 1 exits.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+METRIC = "MLUPS and % of HBM roofline per dtype at 1 GPU; energy error vs FP64"
+
+WORKLOADS = {
+    # name: (builder, q, description)
+    "cavity256_d3q19_bgk": "D3Q19 BGK lid-driven cavity 256^3, lid u=0.1, Re=1000",
+    "tgv512_d3q27_smag": "D3Q27 BGK+Smagorinsky(Cs=0.1) Taylor-Green 512^3, u0=0.05, Re=1600",
+    "porous400_d3q19_trt": "D3Q19 TRT(3/16) body-force porous 400^3, phi=0.20, corr. length 8",
+    "tgv32_d3q19_bgk": "D3Q19 BGK Taylor-Green 32^3, u0=0.04, Re=100 (cache-resident)",
+}
+
+
+def source_hash():
+    """Hash of the kernel sources (to tell whether stored counters still apply)."""
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2506_09242_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def build_workload(name):
+    from paper_2506_09242_amd import inputs
+    if name == "cavity256_d3q19_bgk":
+        n = 256
+        L = n - 2
+        nu = 0.1 * L / 1000.0
+        tags = inputs.cavity_tags(n)
+        kw = dict(q=19, tau=3 * nu + 0.5, wall_velocity=[(0.1, 0.0, 0.0)])
+        return tags, kw, None, None, {"cells": n ** 3, "lid_u": 0.1, "Re": 1000, "cavity_length": L}
+    if name == "tgv512_d3q27_smag":
+        n, u0, Re = 512, 0.05, 1600.0
+        nu = u0 * (n / (2 * np.pi)) / Re
+        rho, u = inputs.tgv3d_fields(n, u0)
+        tags = inputs.all_fluid(n, n, n, inputs.TAG_SMAG)
+        kw = dict(q=27, tau=3 * nu + 0.5, smag_cs=0.1)
+        return tags, kw, rho, u, {"cells": n ** 3, "u0": u0, "Re": Re}
+    if name == "porous400_d3q19_trt":
+        n = 400
+        tags = inputs.porous_tags(n, porosity=0.20, ell=8.0, seed=42)
+        kw = dict(q=19, tau=1.0, trt_lambda=3.0 / 16.0, force=(1e-5, 0.0, 0.0))
+        return tags, kw, None, None, {"cells": n ** 3, "porosity": 0.2, "seed": 42}
+    if name == "tgv32_d3q19_bgk":
+        n, u0 = 32, 0.04
+        rho, u = inputs.tgv3d_fields(n, u0)
+        tags = inputs.all_fluid(n, n, n)
+        kw = dict(q=19, tau=3 * u0 * n / 100.0 + 0.5)
+        return tags, kw, rho, u, {"cells": n ** 3, "u0": u0, "Re": 100}
+    raise SystemExit(f"unknown workload {name}")
+
+
+def alg_bytes_per_launch(tags, q, prec_bytes):
+    """Algorithmic HBM bytes of one collide-stream launch: every fluid node reads
+    and writes its Q populations once; every node's tag byte is read once."""
+    fluid = int(np.isin(tags, (1, 2, 3, 4)).sum())
+    return fluid * 2 * q * prec_bytes + tags.size, fluid
+
+
+def run_dtype(tags, kw, rho, u, prec, steps, warmup, every):
+    import torch
+    from paper_2506_09242_amd import lbm
+    stream = torch.cuda.current_stream()
+    L = lbm.Lattice(tags, prec=prec, stream=stream, **kw)
+    L.init_equilibrium(rho, u)
+    if warmup:
+        L.step(warmup)
+    L.synchronize()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    series = L.step_reduce(steps, every)  # synchronizes at its end
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    _, uf = L.read_fields()
+    variant = L.variant
+    L.close()
+    return {"ms": ms, "wall_s": wall, "series": series, "u": uf, "variant": variant}
+
+
+def cpu_baseline(name, tags, kw, rho, u, steps):
+    import oracle
+    nz, ny, nx = tags.shape
+    okw = {k: v for k, v in kw.items() if k in ("tau", "trt_lambda", "smag_cs", "force", "wall_velocity")}
+    o = oracle.Oracle(nx, ny, nz, q=kw["q"], tags=tags, **okw)
+    o.init_equilibrium(rho, u)
+    o.run(1)  # warm-up (first touch of both arrays)
+    t0 = time.perf_counter()
+    o.run(steps)
+    dt = time.perf_counter() - t0
+    return {"value": tags.size * steps / dt / 1e6, "unit": "MLUPS", "cores": oracle.num_threads(),
+            "kind": "oracle", "sample": f"{steps} FP64 two-population steps of the full {name} lattice "
+                                        f"({tags.size} cells), after 1 warm-up step"}
+
+
+def stored_traffic(workload, prec_name):
+    """HBM bytes per collide-stream launch from committed rocprofv3 counter runs,
+    valid only if the kernel sources are unchanged since they were taken."""
+    p = os.path.join(ROOT, "profiles", f"traffic_{workload}_{prec_name}.json")
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    if d.get("source_hash") != source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--every", type=int, default=100, help="reduction sampling period (steps)")
+    ap.add_argument("--workload", default="cavity256_d3q19_bgk", choices=sorted(WORKLOADS))
+    ap.add_argument("--dtypes", default="f32,f64,f16s", help="first one is the reported value")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(the slab decomposition is design only).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+
+    if args.copy_calibration:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(20):
+            b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        gbs = 2 * (1 << 30) * 20 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+        print(json.dumps({"copy_bytes_read": 1 << 30, "copy_bytes_written": 1 << 30, "copy_GBps": gbs}))
+        return
+
+    from paper_2506_09242_amd import lbm
+    tags, kw, rho, u, wl_cfg = build_workload(args.workload)
+    prec_names = [p.strip() for p in args.dtypes.split(",") if p.strip()]
+    results = {}
+    for pn in prec_names:
+        prec = lbm.PREC_NAMES[pn]
+        r = run_dtype(tags, kw, rho, u, prec, args.steps, args.warmup, args.every)
+        nbytes, nfluid = alg_bytes_per_launch(tags, kw["q"], lbm.PREC_BYTES[prec])
+        launch_s = r["ms"] * 1e-3 / args.steps
+        achieved = nbytes / launch_s / 1e9
+        results[pn] = {"MLUPS": tags.size * args.steps / (r["ms"] * 1e-3) / 1e6,
+                       "MFLUPS_fluid": nfluid * args.steps / (r["ms"] * 1e-3) / 1e6,
+                       "ms_per_step": r["ms"] / args.steps,
+                       "alg_GBps": achieved, "hbm_frac": achieved / HBM_PEAK_GBS,
+                       "bytes_per_launch": nbytes, "variant": r["variant"],
+                       "k_final": r["series"][-1]["kinetic_energy"], "series": r["series"], "u": r["u"],
+                       "wall_s": r["wall_s"]}
+        print(f"# {pn}: {results[pn]['MLUPS']:.1f} MLUPS, {achieved:.1f} GB/s algorithmic "
+              f"({100 * achieved / HBM_PEAK_GBS:.1f}% of 8 TB/s), {r['variant']}", file=sys.stderr, flush=True)
+
+    # errors against the FP64 run
+    errors = {}
+    if "f64" in results:
+        ref = results["f64"]
+        k_ref = np.array([m["kinetic_energy"] for m in ref["series"]])
+        for pn, r in results.items():
+            if pn == "f64":
+                continue
+            k = np.array([m["kinetic_energy"] for m in r["series"]])
+            du = r["u"] - ref["u"]
+            errors[pn] = {"k_rel_err_final": float(abs(k[-1] / k_ref[-1] - 1.0)),
+                          "k_rel_l2_series": float(np.linalg.norm(k - k_ref) / np.linalg.norm(k_ref)),
+                          "u_rel_l2": float(np.linalg.norm(du) / np.linalg.norm(ref["u"])),
+                          "u_max_abs": float(np.abs(du).max())}
+
+    main_p = prec_names[0]
+    m = results[main_p]
+    traffic = stored_traffic(args.workload, main_p)
+    roofline = {"bound": "hbm", "achieved": round(m["alg_GBps"], 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(m["alg_GBps"] / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "k_collide_stream (even/odd AA steps, averaged)",
+                "alg_bytes_per_launch": m["bytes_per_launch"]}
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(args.workload, tags, kw, rho, u, args.cpu_steps)
+
+    line = {
+        "metric": METRIC, "value": round(m["MLUPS"], 2), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(m["ms_per_step"], 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": {"f32": "f32", "f64": "f64", "f16s": "f16-storage/f32"}[main_p],
+        "data": "synthetic",
+        "config": dict({"workload": args.workload, "description": WORKLOADS[args.workload], "q": kw["q"],
+                        "tau": kw["tau"], "storage": main_p + "-shifted", "reduce_every": args.every}, **wl_cfg),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "per_dtype": {pn: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()
+                           if k in ("MLUPS", "MFLUPS_fluid", "ms_per_step", "alg_GBps", "hbm_frac", "variant")}
+                      for pn, r in results.items()},
+        "error_vs_fp64": errors,
+        "kernel_source_hash": source_hash(),
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

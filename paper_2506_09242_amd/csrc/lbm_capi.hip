@@ -1,0 +1,692 @@
+// lbm_capi.hip -- the C ABI (include/lbm.h): lattice object, validation,
+// kernel-variant selection, time stepping, reductions, readback, checkpoint.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lbm.h"
+#include "lbm_device.h"
+#include "lbm_internal.h"
+
+using namespace lbmd;
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_err;
+
+static lbm_status set_err(lbm_status s, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+extern "C" const char *lbm_last_error(void) { return g_err.c_str(); }
+
+// ------------------------------------------------------------------ lattice
+struct lbm_lattice {
+    lbm_config cfg{};
+    hipStream_t stream = nullptr;
+    uint8_t *d_tags = nullptr;
+    double *d_wall = nullptr;       // [16][3]
+    void *d_pops = nullptr;
+    bool own_pops = false;
+    long long stride = 0;           // elements per slot
+    long long ncell = 0;
+    double *d_partials = nullptr;   // [n_tiles][NRED]
+    double *d_series = nullptr;     // [series_cap][NRED]
+    long long series_cap = 0;
+    void *d_mlp = nullptr;          // packed closure block (lbm_mlp.hip)
+    MlpDev mlp{};
+    bool has_mlp = false;
+    long long t = 0;                // time counter
+    int parity = 0;                 // layout parity (0: natural)
+    int ms = MS_BGK;                // compiled model set
+    bool tagged = true;
+    int uniform_tag = LBM_TAG_BGK;
+    int tx_log2 = 8;
+    int tiles_x = 1, tiles_y = 1, n_tiles = 1;
+    long long n_fluid = 0;
+    bool failed = false;
+    char variant[96] = {0};
+};
+
+// Shared with lbm_mlp.hip.
+lbm_status lbmd_fail_hip(lbm_lattice *lat, hipError_t e, const char *what) {
+    if (lat) lat->failed = true;
+    return set_err(LBM_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+lbm_status lbmd_set_err(lbm_status s, const char *msg) { return set_err(s, "%s", msg); }
+
+#define HIPCHK(lat, expr)                                              \
+    do {                                                               \
+        hipError_t e_ = (expr);                                        \
+        if (e_ != hipSuccess) return lbmd_fail_hip((lat), e_, #expr);  \
+    } while (0)
+
+#define CHECK_HANDLE(lat)                                                                    \
+    do {                                                                                     \
+        if (!(lat)) return set_err(LBM_EINVAL, "null lattice handle");                      \
+        if ((lat)->failed) return set_err(LBM_ESTATE, "lattice handle failed earlier");     \
+    } while (0)
+
+// ------------------------------------------------------------ dispatch
+namespace {
+struct Launchers {
+    hipError_t (*step)(const StepParams &, int, bool, int, int, hipStream_t);
+    hipError_t (*init)(const AuxParams &, hipStream_t);
+    hipError_t (*gather)(const AuxParams &, int, hipStream_t);
+    hipError_t (*scatter)(const AuxParams &, hipStream_t);
+};
+
+template <int Q, int P>
+Launchers make_launchers() {
+    return {&launch_step<Q, P>, &launch_init<Q, P>, &launch_gather<Q, P>, &launch_scatter<Q, P>};
+}
+
+Launchers pick(int q, int prec) {
+    if (q == 19) {
+        if (prec == LBM_F64) return make_launchers<19, 0>();
+        if (prec == LBM_F32) return make_launchers<19, 1>();
+        return make_launchers<19, 2>();
+    }
+    if (prec == LBM_F64) return make_launchers<27, 0>();
+    if (prec == LBM_F32) return make_launchers<27, 1>();
+    return make_launchers<27, 2>();
+}
+
+size_t elem_bytes(int prec) { return prec == LBM_F64 ? 8 : (prec == LBM_F32 ? 4 : 2); }
+
+// Slot stride: the plane rounded up to 128 elements plus 128 more, so every
+// slot starts 256-byte aligned and slot bases never sit a power of two apart
+// (which would put all Q streams of a node on the same HBM channel).
+long long slot_stride(long long ncell) { return (ncell + 127) / 128 * 128 + 128; }
+
+bool known_tag(int t) { return (t >= 0 && t <= 4) || (t >= 16 && t <= 31); }
+
+lbm_status validate(const lbm_config *c) {
+    if (!c) return set_err(LBM_EINVAL, "null config");
+    if (c->nx < 1 || c->ny < 1 || c->nz < 1)
+        return set_err(LBM_EINVAL, "lattice size must be >= 1 (got %d x %d x %d)", c->nx, c->ny, c->nz);
+    const long long n = (long long)c->nx * c->ny * c->nz;
+    if (n >= (1LL << 31)) return set_err(LBM_EINVAL, "nx*ny*nz = %lld exceeds 2^31 - 1", n);
+    if (c->q != 19 && c->q != 27) return set_err(LBM_EINVAL, "q must be 19 or 27 (got %d)", c->q);
+    if (c->prec < 0 || c->prec > 2) return set_err(LBM_EINVAL, "unknown precision %d", c->prec);
+    if (c->flags != 0) return set_err(LBM_EINVAL, "flags must be 0");
+    if (!(c->rho0 > 0.0) || !std::isfinite(c->rho0)) return set_err(LBM_EINVAL, "rho0 must be > 0");
+    if (!(c->tau > 0.5) || !std::isfinite(c->tau)) return set_err(LBM_EINVAL, "tau must be > 1/2 (got %g)", c->tau);
+    if (!(c->trt_lambda > 0.0) || !std::isfinite(c->trt_lambda)) return set_err(LBM_EINVAL, "trt_lambda must be > 0");
+    if (!(c->smag_cs >= 0.0) || !std::isfinite(c->smag_cs)) return set_err(LBM_EINVAL, "smag_cs must be >= 0");
+    const double fm = std::sqrt(c->force[0] * c->force[0] + c->force[1] * c->force[1] + c->force[2] * c->force[2]);
+    if (!(fm < 0.3)) return set_err(LBM_EINVAL, "|force| must be < 0.3");
+    for (int k = 0; k < 16; ++k) {
+        const double *u = c->wall_velocity[k];
+        const double um = std::sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+        if (!(um < 0.3)) return set_err(LBM_EINVAL, "|wall_velocity[%d]| must be < 0.3", k);
+    }
+    return LBM_OK;
+}
+
+void choose_tiles(lbm_lattice *L, int txl) {
+    L->tx_log2 = txl;
+    const int TX = 1 << txl, TY = 256 >> txl;
+    L->tiles_x = (L->cfg.nx + TX - 1) / TX;
+    L->tiles_y = (L->cfg.ny + TY - 1) / TY;
+    L->n_tiles = L->tiles_x * L->tiles_y * L->cfg.nz;
+}
+
+// Default tile width: the smallest padded row (ceil(nx/tx)*tx), larger tx on ties.
+int default_txl(int nx) {
+    int best = 8;
+    long long best_pad = (long long)((nx + 255) / 256) * 256;
+    for (int l = 7; l >= 5; --l) {
+        const int tx = 1 << l;
+        const long long pad = (long long)((nx + tx - 1) / tx) * tx;
+        if (pad < best_pad) {
+            best_pad = pad;
+            best = l;
+        }
+    }
+    return best;
+}
+
+StepParams step_params(const lbm_lattice *L) {
+    StepParams p{};
+    const lbm_config &c = L->cfg;
+    p.pops = L->d_pops;
+    p.tags = L->d_tags;
+    p.wall_u = L->d_wall;
+    p.partials = L->d_partials;
+    p.stride = L->stride;
+    p.nx = c.nx;
+    p.ny = c.ny;
+    p.nz = c.nz;
+    p.tiles_x = L->tiles_x;
+    p.tiles_y = L->tiles_y;
+    p.n_tiles = L->n_tiles;
+    p.tiles_per_xcd = (L->n_tiles + 7) / 8;
+    p.tx_log2 = L->tx_log2;
+    p.uniform_tag = L->uniform_tag;
+    p.has_force = (c.force[0] != 0.0 || c.force[1] != 0.0 || c.force[2] != 0.0) ? 1 : 0;
+    p.has_mlp = L->has_mlp ? 1 : 0;
+    p.rho0 = c.rho0;
+    p.tau = c.tau;
+    p.omega = 1.0 / c.tau;
+    p.omega_minus = 1.0 / (0.5 + c.trt_lambda / (c.tau - 0.5));
+    p.smag_c = 18.0 * std::sqrt(2.0) * c.smag_cs * c.smag_cs;
+    p.nu0 = (c.tau - 0.5) / 3.0;
+    for (int a = 0; a < 3; ++a) p.force[a] = c.force[a];
+    p.mlp = L->mlp;
+    return p;
+}
+
+AuxParams aux_params(const lbm_lattice *L) {
+    AuxParams a{};
+    a.pops = L->d_pops;
+    a.tags = L->d_tags;
+    a.stride = L->stride;
+    a.nx = L->cfg.nx;
+    a.ny = L->cfg.ny;
+    a.nz = L->cfg.nz;
+    a.parity = L->parity;
+    a.rho0 = L->cfg.rho0;
+    for (int k = 0; k < 3; ++k) a.force[k] = L->cfg.force[k];
+    return a;
+}
+
+// Nodes per staging chunk: whole z-planes, at most ~256 MB of doubles.
+long long chunk_cells(const lbm_lattice *L, int per_cell_doubles) {
+    const long long plane = (long long)L->cfg.nx * L->cfg.ny;
+    const long long cap = std::max(1LL, (256LL << 20) / (8LL * per_cell_doubles) / plane);
+    return std::min<long long>(cap, L->cfg.nz) * plane;
+}
+
+struct DevBuf {
+    void *p = nullptr;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+};
+}  // namespace
+
+// ---------------------------------------------------------- finalize kernel
+namespace lbmd {
+// Fixed-order sum of the per-tile partials: Neumaier per thread over a
+// strided subset, then a pairwise tree in LDS.
+__global__ __launch_bounds__(256) void k_finalize(const double *part, int nt, double *out) {
+    __shared__ double s[256];
+    const int t = threadIdx.x;
+    for (int k = 0; k < NRED; ++k) {
+        double sum = 0.0, comp = 0.0;
+        for (int b = t; b < nt; b += 256) {
+            const double v = part[(long long)b * NRED + k];
+            const double u = sum + v;
+            comp += (fabs(sum) >= fabs(v)) ? (sum - u) + v : (v - u) + sum;
+            sum = u;
+        }
+        s[t] = sum + comp;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if (t < w) s[t] += s[t + w];
+            __syncthreads();
+        }
+        if (t == 0) out[k] = s[0];
+        __syncthreads();
+    }
+}
+
+hipError_t launch_finalize(const double *partials, int n_tiles, double *out, hipStream_t s) {
+    k_finalize<<<1, 256, 0, s>>>(partials, n_tiles, out);
+    return hipGetLastError();
+}
+}  // namespace lbmd
+
+// ------------------------------------------------------------------ create
+extern "C" size_t lbm_population_bytes(const lbm_config *cfg) {
+    if (validate(cfg) != LBM_OK) return 0;
+    const long long n = (long long)cfg->nx * cfg->ny * cfg->nz;
+    return (size_t)cfg->q * (size_t)slot_stride(n) * elem_bytes(cfg->prec);
+}
+
+static lbm_status create_impl(const lbm_config *cfg, const uint8_t *tags_host, void *pops_dev, size_t pops_bytes,
+                              void *stream, lbm_lattice **out) {
+    if (!out) return set_err(LBM_EINVAL, "null output handle");
+    *out = nullptr;
+    lbm_status s = validate(cfg);
+    if (s != LBM_OK) return s;
+    if (!tags_host) return set_err(LBM_EINVAL, "null tags");
+    const long long N = (long long)cfg->nx * cfg->ny * cfg->nz;
+
+    // Tag histogram: validity, fluid count, model set, geometry.
+    long long hist[32] = {0};
+    for (long long n = 0; n < N; ++n) {
+        const int t = tags_host[n];
+        if (!known_tag(t)) return set_err(LBM_EINVAL, "unknown tag value %d at node %lld", t, n);
+        hist[t]++;
+    }
+    long long nf = hist[1] + hist[2] + hist[3] + hist[4];
+    if (nf == 0) return set_err(LBM_EINVAL, "no fluid node");
+    int need = 0;
+    if (hist[LBM_TAG_BGK]) need |= MS_BGK;
+    if (hist[LBM_TAG_TRT]) need |= MS_TRT;
+    if (hist[LBM_TAG_BGK_SMAG]) need |= MS_SMAG;
+    if (hist[LBM_TAG_BGK_MLP]) need |= MS_MLP;
+    int ms = -1;
+    for (int k = 0; k < kNumModelSets; ++k)
+        if ((kModelSets[k] & need) == need) {
+            ms = kModelSets[k];
+            break;
+        }
+    if (ms < 0) return set_err(LBM_EUNSUPPORTED, "no compiled model set covers the tags");
+    int n_models = 0, only = LBM_TAG_BGK;
+    for (int t = 1; t <= 4; ++t)
+        if (hist[t]) {
+            n_models++;
+            only = t;
+        }
+    const bool tagged = !(nf == N && n_models == 1);
+
+    const size_t need_bytes = lbm_population_bytes(cfg);
+    if (pops_dev) {
+        if (pops_bytes < need_bytes)
+            return set_err(LBM_EINVAL, "population buffer has %zu bytes, needs %zu", pops_bytes, need_bytes);
+        if (reinterpret_cast<uintptr_t>(pops_dev) % 256 != 0)
+            return set_err(LBM_EINVAL, "population buffer must be 256-byte aligned");
+    }
+
+    lbm_lattice *L = new (std::nothrow) lbm_lattice();
+    if (!L) return set_err(LBM_ENOMEM, "host allocation failed");
+    L->cfg = *cfg;
+    L->stream = static_cast<hipStream_t>(stream);
+    L->ncell = N;
+    L->stride = slot_stride(N);
+    L->n_fluid = nf;
+    L->ms = ms;
+    L->tagged = tagged;
+    L->uniform_tag = only;
+    choose_tiles(L, default_txl(cfg->nx));
+    static const char *msname[] = {"bgk", "trt", "bgk+smag", "bgk+smag+mlp", "all"};
+    int msi = 0;
+    for (int k = 0; k < kNumModelSets; ++k)
+        if (kModelSets[k] == ms) msi = k;
+    snprintf(L->variant, sizeof L->variant, "D3Q%d/%s/%s/%s", cfg->q,
+             cfg->prec == LBM_F64 ? "f64" : (cfg->prec == LBM_F32 ? "f32" : "f16s"), msname[msi],
+             tagged ? "tagged" : "uniform");
+
+    auto bail = [&](lbm_status st) {
+        lbm_destroy(L);
+        return st;
+    };
+    hipError_t e;
+    if (pops_dev) {
+        L->d_pops = pops_dev;
+        L->own_pops = false;
+    } else {
+        e = hipMalloc(&L->d_pops, need_bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            L->d_pops = nullptr;
+            return bail(set_err(LBM_ENOMEM, "hipMalloc of %zu population bytes failed: %s", need_bytes,
+                                hipGetErrorString(e)));
+        }
+        L->own_pops = true;
+    }
+    e = hipMalloc(&L->d_tags, (size_t)N);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        L->d_tags = nullptr;
+        return bail(set_err(LBM_ENOMEM, "hipMalloc of tags failed"));
+    }
+    e = hipMalloc(&L->d_wall, 16 * 3 * sizeof(double));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        L->d_wall = nullptr;
+        return bail(set_err(LBM_ENOMEM, "hipMalloc of wall table failed"));
+    }
+    // Partials sized for the tiling with the most tiles over every allowed tile width.
+    long long max_tiles = 0;
+    for (int l = 5; l <= 8; ++l) {
+        const long long tx = 1LL << l, ty = 256 >> l;
+        max_tiles = std::max(max_tiles, ((cfg->nx + tx - 1) / tx) * ((cfg->ny + ty - 1) / ty) * cfg->nz);
+    }
+    e = hipMalloc(&L->d_partials, (size_t)max_tiles * NRED * sizeof(double));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        L->d_partials = nullptr;
+        return bail(set_err(LBM_ENOMEM, "hipMalloc of reduction partials failed"));
+    }
+    e = hipMemcpyAsync(L->d_tags, tags_host, (size_t)N, hipMemcpyHostToDevice, L->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(L->d_wall, cfg->wall_velocity, 16 * 3 * sizeof(double), hipMemcpyHostToDevice, L->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+    if (e != hipSuccess) return bail(lbmd_fail_hip(nullptr, e, "tag upload"));
+    *out = L;
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_create(const lbm_config *cfg, const uint8_t *tags_host, void *hip_stream,
+                                 lbm_lattice **out) {
+    return create_impl(cfg, tags_host, nullptr, 0, hip_stream, out);
+}
+
+extern "C" lbm_status lbm_create_on_buffer(const lbm_config *cfg, const uint8_t *tags_host, void *pops_dev,
+                                           size_t pops_bytes, void *hip_stream, lbm_lattice **out) {
+    if (!pops_dev) return set_err(LBM_EINVAL, "null population buffer");
+    return create_impl(cfg, tags_host, pops_dev, pops_bytes, hip_stream, out);
+}
+
+void lbmd_free_mlp(lbm_lattice *lat);  // lbm_mlp.hip
+
+extern "C" void lbm_destroy(lbm_lattice *lat) {
+    if (!lat) return;
+    if (lat->stream || lat->d_pops) (void)hipStreamSynchronize(lat->stream);
+    if (lat->own_pops && lat->d_pops) (void)hipFree(lat->d_pops);
+    if (lat->d_tags) (void)hipFree(lat->d_tags);
+    if (lat->d_wall) (void)hipFree(lat->d_wall);
+    if (lat->d_partials) (void)hipFree(lat->d_partials);
+    if (lat->d_series) (void)hipFree(lat->d_series);
+    lbmd_free_mlp(lat);
+    delete lat;
+}
+
+extern "C" lbm_status lbm_set_launch(lbm_lattice *lat, int tx, int ty) {
+    CHECK_HANDLE(lat);
+    int l = -1;
+    for (int k = 5; k <= 8; ++k)
+        if (tx == (1 << k)) l = k;
+    if (l < 0 || tx * ty != 256) return set_err(LBM_EINVAL, "tile must be tx in {32,64,128,256} with tx*ty = 256");
+    choose_tiles(lat, l);
+    return LBM_OK;
+}
+
+extern "C" const char *lbm_variant_name(const lbm_lattice *lat) { return lat ? lat->variant : ""; }
+
+extern "C" int64_t lbm_time(const lbm_lattice *lat) { return lat ? lat->t : -1; }
+
+extern "C" lbm_status lbm_synchronize(lbm_lattice *lat) {
+    CHECK_HANDLE(lat);
+    HIPCHK(lat, hipStreamSynchronize(lat->stream));
+    return LBM_OK;
+}
+
+extern "C" int lbm_velocity(int q, int i, int c[3], double *w) {
+    if ((q != 19 && q != 27) || i < 0 || i >= q || !c || !w) return -1;
+    // The device tables are compile-time; mirror them through a small host loop.
+    int out = -1;
+    auto fill = [&](auto I) {
+        constexpr int k = decltype(I)::value;
+        if (k == i) {
+            if (q == 19) {
+                if constexpr (k < 19) {
+                    using Vk = V<19, k>;
+                    c[0] = Vk::x, c[1] = Vk::y, c[2] = Vk::z, *w = Vk::w, out = Vk::opp;
+                }
+            } else {
+                using Vk = V<27, k>;
+                c[0] = Vk::x, c[1] = Vk::y, c[2] = Vk::z, *w = Vk::w, out = Vk::opp;
+            }
+        }
+    };
+    [&]<int... Is>(std::integer_sequence<int, Is...>) { (fill(std::integral_constant<int, Is>{}), ...); }(
+        std::make_integer_sequence<int, 27>{});
+    return out;
+}
+
+// ------------------------------------------------------------ initial state
+extern "C" lbm_status lbm_init_equilibrium(lbm_lattice *lat, const double *rho_host, const double *u_host) {
+    CHECK_HANDLE(lat);
+    const long long N = lat->ncell;
+    const long long chunk = chunk_cells(lat, 4);
+    DevBuf buf;
+    HIPCHK(lat, hipMalloc(&buf.p, (size_t)chunk * 4 * sizeof(double)));
+    double *d = static_cast<double *>(buf.p);
+    const Launchers Lc = pick(lat->cfg.q, lat->cfg.prec);
+    for (long long c0 = 0; c0 < N; c0 += chunk) {
+        const long long cnt = std::min(chunk, N - c0);
+        AuxParams a = aux_params(lat);
+        a.cell0 = c0;
+        a.count = cnt;
+        a.in_rho = nullptr;
+        a.in_u = nullptr;
+        if (rho_host) {
+            HIPCHK(lat, hipMemcpyAsync(d, rho_host + c0, cnt * sizeof(double), hipMemcpyHostToDevice, lat->stream));
+            a.in_rho = d;
+        }
+        if (u_host) {
+            for (int k = 0; k < 3; ++k)
+                HIPCHK(lat, hipMemcpyAsync(d + (1 + k) * cnt, u_host + k * N + c0, cnt * sizeof(double),
+                                           hipMemcpyHostToDevice, lat->stream));
+            a.in_u = d + cnt;
+        }
+        HIPCHK(lat, Lc.init(a, lat->stream));
+        HIPCHK(lat, hipStreamSynchronize(lat->stream));
+    }
+    lat->t = 0;
+    lat->parity = 0;
+    return LBM_OK;
+}
+
+// --------------------------------------------------------------- stepping
+static lbm_status launch_one(lbm_lattice *lat, int mode) {
+    const Launchers Lc = pick(lat->cfg.q, lat->cfg.prec);
+    const StepParams p = step_params(lat);
+    HIPCHK(lat, Lc.step(p, lat->ms, lat->tagged, mode, lat->parity, lat->stream));
+    if (mode != MODE_REDUCE) {
+        lat->parity ^= 1;
+        lat->t += 1;
+    }
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_step(lbm_lattice *lat, int64_t n_steps) {
+    CHECK_HANDLE(lat);
+    if (n_steps < 0) return set_err(LBM_EINVAL, "n_steps must be >= 0");
+    for (int64_t s = 0; s < n_steps; ++s) {
+        lbm_status st = launch_one(lat, MODE_STEP);
+        if (st != LBM_OK) return st;
+    }
+    return LBM_OK;
+}
+
+static lbm_status ensure_series(lbm_lattice *lat, long long n) {
+    if (n <= lat->series_cap) return LBM_OK;
+    if (lat->d_series) {
+        HIPCHK(lat, hipStreamSynchronize(lat->stream));
+        HIPCHK(lat, hipFree(lat->d_series));
+        lat->d_series = nullptr;
+    }
+    HIPCHK(lat, hipMalloc(&lat->d_series, (size_t)n * NRED * sizeof(double)));
+    lat->series_cap = n;
+    return LBM_OK;
+}
+
+static void fill_moments(const lbm_lattice *lat, const double *v, int64_t step, lbm_moments *m) {
+    m->step = step;
+    m->n_fluid = lat->n_fluid;
+    m->n_nonfinite = (int64_t)std::llround(v[9]);
+    m->mass_delta = v[0];
+    m->mass = (double)lat->n_fluid * lat->cfg.rho0 + v[0];
+    for (int a = 0; a < 3; ++a) {
+        m->momentum[a] = v[1 + a];
+        m->velocity_sum[a] = v[4 + a];
+    }
+    m->kinetic_energy = v[7] / (double)lat->n_fluid;
+    m->kinetic_energy_rho = v[8];
+}
+
+extern "C" lbm_status lbm_step_reduce(lbm_lattice *lat, int64_t n_steps, int64_t every, lbm_moments *series,
+                                      int64_t n_series) {
+    CHECK_HANDLE(lat);
+    if (n_steps < 0 || every < 1) return set_err(LBM_EINVAL, "need n_steps >= 0 and every >= 1");
+    const int64_t ns = n_steps / every + 1;
+    if (!series || n_series < ns) return set_err(LBM_EINVAL, "series needs %lld entries", (long long)ns);
+    lbm_status st = ensure_series(lat, ns);
+    if (st != LBM_OK) return st;
+    const int64_t t0 = lat->t;
+    for (int64_t s = 0; s < n_steps; ++s) {
+        if (s % every == 0) {
+            st = launch_one(lat, MODE_STEP_REDUCE);
+            if (st != LBM_OK) return st;
+            HIPCHK(lat, launch_finalize(lat->d_partials, lat->n_tiles, lat->d_series + (s / every) * NRED,
+                                        lat->stream));
+        } else {
+            st = launch_one(lat, MODE_STEP);
+            if (st != LBM_OK) return st;
+        }
+    }
+    if (n_steps % every == 0) {
+        st = launch_one(lat, MODE_REDUCE);
+        if (st != LBM_OK) return st;
+        HIPCHK(lat, launch_finalize(lat->d_partials, lat->n_tiles, lat->d_series + (ns - 1) * NRED, lat->stream));
+    }
+    std::vector<double> h((size_t)ns * NRED);
+    HIPCHK(lat, hipMemcpyAsync(h.data(), lat->d_series, h.size() * sizeof(double), hipMemcpyDeviceToHost,
+                               lat->stream));
+    HIPCHK(lat, hipStreamSynchronize(lat->stream));
+    bool bad = false;
+    for (int64_t k = 0; k < ns; ++k) {
+        fill_moments(lat, h.data() + k * NRED, t0 + k * every, &series[k]);
+        if (series[k].n_nonfinite > 0) bad = true;
+    }
+    if (bad) return set_err(LBM_EUNSTABLE, "non-finite density or velocity found");
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_reduce(lbm_lattice *lat, lbm_moments *out) {
+    CHECK_HANDLE(lat);
+    if (!out) return set_err(LBM_EINVAL, "null output");
+    return lbm_step_reduce(lat, 0, 1, out, 1);
+}
+
+// ---------------------------------------------------------------- readback
+static lbm_status gather_range(lbm_lattice *lat, int gmode, double *host, int per_cell) {
+    const long long N = lat->ncell;
+    const long long chunk = chunk_cells(lat, per_cell);
+    DevBuf buf;
+    HIPCHK(lat, hipMalloc(&buf.p, (size_t)chunk * per_cell * sizeof(double)));
+    double *d = static_cast<double *>(buf.p);
+    const Launchers Lc = pick(lat->cfg.q, lat->cfg.prec);
+    for (long long c0 = 0; c0 < N; c0 += chunk) {
+        const long long cnt = std::min(chunk, N - c0);
+        AuxParams a = aux_params(lat);
+        a.cell0 = c0;
+        a.count = cnt;
+        a.out = d;
+        HIPCHK(lat, Lc.gather(a, gmode, lat->stream));
+        for (int k = 0; k < per_cell; ++k)
+            HIPCHK(lat, hipMemcpyAsync(host + k * N + c0, d + k * cnt, cnt * sizeof(double), hipMemcpyDeviceToHost,
+                                       lat->stream));
+        HIPCHK(lat, hipStreamSynchronize(lat->stream));
+    }
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_read_fields(lbm_lattice *lat, double *rho_host, double *u_host) {
+    CHECK_HANDLE(lat);
+    if (!rho_host && !u_host) return LBM_OK;
+    const long long N = lat->ncell;
+    std::vector<double> tmp;
+    double *dst;
+    try {
+        tmp.resize((size_t)N * 4);
+    } catch (...) {
+        return set_err(LBM_ENOMEM, "host allocation failed");
+    }
+    dst = tmp.data();
+    lbm_status st = gather_range(lat, G_FIELDS, dst, 4);
+    if (st != LBM_OK) return st;
+    if (rho_host) std::memcpy(rho_host, dst, (size_t)N * sizeof(double));
+    if (u_host) std::memcpy(u_host, dst + N, (size_t)N * 3 * sizeof(double));
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_read_populations(lbm_lattice *lat, double *f_host) {
+    CHECK_HANDLE(lat);
+    if (!f_host) return set_err(LBM_EINVAL, "null output");
+    return gather_range(lat, G_POPS, f_host, lat->cfg.q);
+}
+
+extern "C" lbm_status lbm_read_cells(lbm_lattice *lat, const int64_t *cells_host, int64_t n, double *f_host) {
+    CHECK_HANDLE(lat);
+    if (n < 0 || (n > 0 && (!cells_host || !f_host))) return set_err(LBM_EINVAL, "bad cell list");
+    if (n == 0) return LBM_OK;
+    for (int64_t k = 0; k < n; ++k)
+        if (cells_host[k] < 0 || cells_host[k] >= lat->ncell)
+            return set_err(LBM_EINVAL, "cell index %lld out of range", (long long)cells_host[k]);
+    const int q = lat->cfg.q;
+    DevBuf buf;
+    HIPCHK(lat, hipMalloc(&buf.p, (size_t)n * (q + 1) * sizeof(double)));
+    long long *dc = static_cast<long long *>(buf.p);
+    double *dout = reinterpret_cast<double *>(dc + n);
+    HIPCHK(lat, hipMemcpyAsync(dc, cells_host, (size_t)n * sizeof(int64_t), hipMemcpyHostToDevice, lat->stream));
+    AuxParams a = aux_params(lat);
+    a.cells = dc;
+    a.count = n;
+    a.out = dout;
+    HIPCHK(lat, pick(q, lat->cfg.prec).gather(a, G_CELLS, lat->stream));
+    HIPCHK(lat, hipMemcpyAsync(f_host, dout, (size_t)n * q * sizeof(double), hipMemcpyDeviceToHost, lat->stream));
+    HIPCHK(lat, hipStreamSynchronize(lat->stream));
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_write_populations(lbm_lattice *lat, const double *f_host, int64_t t) {
+    CHECK_HANDLE(lat);
+    if (!f_host) return set_err(LBM_EINVAL, "null input");
+    if (t < 0) return set_err(LBM_EINVAL, "time must be >= 0");
+    const int q = lat->cfg.q;
+    const long long N = lat->ncell;
+    const long long chunk = chunk_cells(lat, q);
+    DevBuf buf;
+    HIPCHK(lat, hipMalloc(&buf.p, (size_t)chunk * q * sizeof(double)));
+    double *d = static_cast<double *>(buf.p);
+    const Launchers Lc = pick(q, lat->cfg.prec);
+    for (long long c0 = 0; c0 < N; c0 += chunk) {
+        const long long cnt = std::min(chunk, N - c0);
+        for (int k = 0; k < q; ++k)
+            HIPCHK(lat, hipMemcpyAsync(d + k * cnt, f_host + k * N + c0, cnt * sizeof(double), hipMemcpyHostToDevice,
+                                       lat->stream));
+        AuxParams a = aux_params(lat);
+        a.cell0 = c0;
+        a.count = cnt;
+        a.in_f = d;
+        HIPCHK(lat, Lc.scatter(a, lat->stream));
+        HIPCHK(lat, hipStreamSynchronize(lat->stream));
+    }
+    lat->parity = 0;
+    lat->t = t;
+    return LBM_OK;
+}
+
+// ------------------------------------------------- accessors for lbm_mlp.hip
+lbm_config lbmd_config(const lbm_lattice *lat) { return lat->cfg; }
+hipStream_t lbmd_stream(const lbm_lattice *lat) { return lat->stream; }
+bool lbmd_failed(const lbm_lattice *lat) { return lat->failed; }
+void lbmd_set_mlp(lbm_lattice *lat, void *block, const MlpDev &m) {
+    lat->d_mlp = block;
+    lat->mlp = m;
+    lat->has_mlp = true;
+}
+void *lbmd_mlp_block(lbm_lattice *lat) { return lat->d_mlp; }
+void lbmd_clear_mlp(lbm_lattice *lat) {
+    lat->d_mlp = nullptr;
+    lat->has_mlp = false;
+}
+// Natural-state gather of the whole lattice into device memory (FP64,
+// `per_cell` = 4 fields: rho, ux, uy, uz as planes).  Used by the filter.
+lbm_status lbmd_fields_device(lbm_lattice *lat, double *d_out) {
+    AuxParams a = aux_params(lat);
+    a.cell0 = 0;
+    a.count = lat->ncell;
+    a.out = d_out;
+    HIPCHK(lat, pick(lat->cfg.q, lat->cfg.prec).gather(a, G_FIELDS, lat->stream));
+    return LBM_OK;
+}

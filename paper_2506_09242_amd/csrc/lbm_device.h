@@ -1,0 +1,70 @@
+// lbm_device.h -- device-side lattice tables and compile-time loop helper.
+//
+// Canonical velocity order (the ABI's): rest; +x,+y,+z; face diagonals
+// (1,1,0),(1,-1,0),(1,0,1),(1,0,-1),(0,1,1),(0,1,-1); D3Q27 corners
+// (1,1,1),(1,1,-1),(1,-1,1),(1,-1,-1); then the negatives in the same order,
+// so the opposite of i in 1..H is i+H (H = (Q-1)/2).  Weights are the
+// textbook D3Q19 (1/3, 1/18, 1/36) and D3Q27 (8/27, 2/27, 1/54, 1/216) ones,
+// c_s^2 = 1/3.  Every index is a compile-time constant, so the tables fold
+// into immediates.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+#include <utility>
+
+namespace lbmd {
+
+constexpr int kHalfDirs[13][3] = {
+    {1, 0, 0},  {0, 1, 0},  {0, 0, 1},  {1, 1, 0},  {1, -1, 0}, {1, 0, 1},  {1, 0, -1},
+    {0, 1, 1},  {0, 1, -1}, {1, 1, 1},  {1, 1, -1}, {1, -1, 1}, {1, -1, -1}};
+
+template <int Q, int I>
+struct V {
+    static_assert(Q == 19 || Q == 27, "D3Q19 or D3Q27");
+    static constexpr int H = (Q - 1) / 2;
+    static constexpr int k = I == 0 ? 0 : (I <= H ? I - 1 : I - 1 - H);
+    static constexpr int s = I == 0 ? 0 : (I <= H ? 1 : -1);
+    static constexpr int x = s * kHalfDirs[k][0];
+    static constexpr int y = s * kHalfDirs[k][1];
+    static constexpr int z = s * kHalfDirs[k][2];
+    static constexpr int opp = I == 0 ? 0 : (I <= H ? I + H : I - H);
+    static constexpr int n2 = x * x + y * y + z * z;
+    static constexpr double w =
+        Q == 19 ? (n2 == 0 ? 1.0 / 3.0 : (n2 == 1 ? 1.0 / 18.0 : 1.0 / 36.0))
+                : (n2 == 0 ? 8.0 / 27.0 : (n2 == 1 ? 2.0 / 27.0 : (n2 == 2 ? 1.0 / 54.0 : 1.0 / 216.0)));
+};
+
+template <typename F, int... Is>
+__device__ __forceinline__ void sfor_impl(F &&f, std::integer_sequence<int, Is...>) {
+    (f(std::integral_constant<int, Is>{}), ...);
+}
+// Calls f(integral_constant<int, i>) for i = 0 .. N-1 (fully unrolled).
+template <int N, typename F>
+__device__ __forceinline__ void sfor(F &&f) {
+    sfor_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+__device__ __forceinline__ bool is_fluid_tag(int t) { return t >= 1 && t <= 4; }
+
+// Storage / compute types per precision (lbm_prec).
+template <int P>
+struct Prec;
+template <>
+struct Prec<0> {
+    using S = double;
+    using C = double;
+};
+template <>
+struct Prec<1> {
+    using S = float;
+    using C = float;
+};
+template <>
+struct Prec<2> {
+    using S = _Float16;
+    using C = float;
+};
+
+}  // namespace lbmd

@@ -1,0 +1,112 @@
+// lbm_internal.h -- host/device shared declarations of the HIP library.
+//
+// Parameter blocks passed by value to the kernels, and the per-(Q, precision)
+// launcher entry points.  Each launcher lives in its own translation unit
+// (lbm_q{19,27}_{f64,f32,f16}.hip) so the kernel variants compile in parallel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "lbm.h"
+
+namespace lbmd {
+
+// Collision-model sets a step kernel can be specialised on (the kernel-size
+// reduction of Sec. 2.3: only the models present are compiled in).
+enum ModelSet : int {
+    MS_BGK = 1,
+    MS_TRT = 2,
+    MS_SMAG = 4,
+    MS_MLP = 8,
+};
+
+// Compiled model-set variants, smallest first.  The host picks the first one
+// that covers the fluid tags present.
+constexpr int kModelSets[] = {MS_BGK, MS_TRT, MS_BGK | MS_SMAG, MS_BGK | MS_SMAG | MS_MLP,
+                              MS_BGK | MS_TRT | MS_SMAG | MS_MLP};
+constexpr int kNumModelSets = 5;
+
+// Kernel modes.
+enum StepMode : int {
+    MODE_STEP = 0,        // collide + stream
+    MODE_STEP_REDUCE = 1, // collide + stream + reductions of the loaded state
+    MODE_REDUCE = 2,      // reductions of the current state only (no stores)
+};
+
+// Reduction slots per sample: sum drho, sum rho u (3), sum u (3), sum u^2/2,
+// sum rho u^2/2, count of non-finite nodes.
+constexpr int NRED = 10;
+
+// Packed closure parameters on the device: BF16 weights (as uint16 bit
+// patterns) followed by FP32 biases and normalisation (see lbm_mlp.hip).
+struct MlpDev {
+    const uint16_t *w1;   // [32][8]: W1 rows padded from 7 to 8 inputs (zero)
+    const uint16_t *w2;   // [2 m-tiles][4 lane groups][16 rows][8 slots], columns
+                          // permuted to the layer-1 accumulator order
+    const float *b1;      // [32]
+    const float *b2;      // [32]
+    const float *w3;      // [32] FP32 copy of the BF16-rounded W3
+    const float *b3;      // [1]
+    const float *mean;    // [7]
+    const float *sd;      // [7] standard deviations
+};
+
+struct StepParams {
+    void *pops;               // population array, Q slots of `stride` elements
+    const uint8_t *tags;      // device tags (TAGGED variants)
+    const double *wall_u;     // [16][3] moving-wall velocities (device)
+    double *partials;         // [n_tiles][NRED] per-tile reduction partials
+    long long stride;         // elements per population slot (padded plane)
+    int nx, ny, nz;
+    int tiles_x, tiles_y;     // tile grid in x and y (z: one plane per tile row)
+    int n_tiles;              // tiles_x * tiles_y * nz
+    int tiles_per_xcd;        // ceil(n_tiles / 8)
+    int tx_log2;              // tile width = 1 << tx_log2, height = 256 >> tx_log2
+    int uniform_tag;          // model tag of every node (untagged variants)
+    int has_force;
+    int has_mlp;              // closure parameters uploaded
+    double rho0;
+    double tau;               // tau (BGK) = tau_plus (TRT)
+    double omega;             // 1 / tau
+    double omega_minus;       // TRT: 1 / (1/2 + Lambda / (tau - 1/2))
+    double smag_c;            // 18 sqrt(2) Cs^2 (implicit Smagorinsky)
+    double nu0;               // (tau - 1/2) / 3
+    double force[3];
+    MlpDev mlp;
+};
+
+// Parameters of the off-step helpers (initialisation, gathers, scatters).
+struct AuxParams {
+    void *pops;
+    const uint8_t *tags;
+    long long stride;
+    int nx, ny, nz;
+    int parity;               // layout parity of the state (0: natural)
+    double rho0;
+    double force[3];
+    long long cell0;          // first node of the chunk (range modes)
+    long long count;          // nodes in the chunk / in the list
+    const long long *cells;   // node list (list mode) or null
+    const double *in_rho;     // init: nullable
+    const double *in_u;       // init: nullable, 3 planes of `count`
+    const double *in_f;       // scatter: Q planes of `count`
+    double *out;              // gather output
+};
+
+enum GatherMode : int { G_POPS = 0, G_FIELDS = 1, G_CELLS = 2 };
+
+template <int Q, int P>
+hipError_t launch_step(const StepParams &p, int ms, bool tagged, int mode, int parity, hipStream_t s);
+template <int Q, int P>
+hipError_t launch_init(const AuxParams &a, hipStream_t s);
+template <int Q, int P>
+hipError_t launch_gather(const AuxParams &a, int gmode, hipStream_t s);
+template <int Q, int P>
+hipError_t launch_scatter(const AuxParams &a, hipStream_t s);
+
+hipError_t launch_finalize(const double *partials, int n_tiles, double *out, hipStream_t s);
+
+}  // namespace lbmd

@@ -1,0 +1,494 @@
+// lbm_kernels.h -- the fused collide-and-stream kernel and its helpers.
+//
+// Included by one translation unit per (Q, precision); each instantiates the
+// launchers declared in lbm_internal.h.
+//
+// In-place streaming: the AA pattern (named in Sec. 2.3 of the paper as the
+// single-array, thread-safe alternative to the two-population scheme).
+// With h_i(x) the population of direction i at node x stored in slot i:
+//   even step  : read slot i at x; collide; write h*_i to slot opp(i) at x.
+//   odd step   : read h_i(x) from slot opp(i) at x - c_i; collide; write h*_i
+//                to slot i at x + c_i.
+// After an even step the array holds the next state "in reverse"; after the
+// odd step it is back in natural layout.  Each (node, slot) is read and
+// written by exactly one thread per step, so the update is race-free.
+// Half-way bounce-back (Sec. 3 intro, after Ladd) closes the loop next to a
+// non-fluid node y = x + c_i: the post-collision h*_i returns to node x as
+// direction opp(i), minus 6 w_i rho0 (c_i . u_wall) for a moving wall; in
+// the even step that value already sits in slot opp(i) at x (so the wall
+// term is applied there), in the odd step it is written to slot opp(i) at x,
+// and the odd step's read of direction i from a wall neighbour x - c_i
+// takes slot i at x instead.
+//
+// Node update (Sec. 2.3 push-pull scheme): the Q populations of a node are
+// pulled into registers, the tag selects the collision model (switch over
+// the compiled model set), and the results are pushed back.  Populations are
+// stored shifted, h_i = f_i - w_i rho0 (Sec. 3 intro, Skordos' offset
+// stripping), which the collision is written for directly:
+//   drho = sum h_i, rho = rho0 + drho, j = sum c_i h_i, u = (j + F/2) / rho
+//   heq_i = w_i (drho + rho (3 c.u + 9/2 (c.u)^2 - 3/2 u.u))
+// and the collision works on pairs (i, opp(i)) split into even and odd parts
+// (TRT; BGK is the case omega- = omega+), with the Guo forcing term split
+// the same way.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "lbm_device.h"
+#include "lbm_internal.h"
+#include "lbm_mlp_device.h"
+
+namespace lbmd {
+
+// Largest tag tile staged in LDS: (tx+2)*(ty+2)*3 over tx in {32..256}.
+constexpr int kTileBytes = 2336;
+
+__device__ __forceinline__ int wrap_idx(int v, int n) { return v < 0 ? v + n : (v >= n ? v % n : v); }
+
+template <int Q, int P, int MS, bool TAGGED, int MODE, int PARITY>
+__global__ __launch_bounds__(256) void k_collide_stream(StepParams p) {
+    using S = typename Prec<P>::S;
+    using C = typename Prec<P>::C;
+    constexpr int H = (Q - 1) / 2;
+
+    // XCD-aware tile order: hardware deals workgroups round-robin over the 8
+    // XCDs, so workgroup w runs on XCD w % 8; give each XCD a contiguous run
+    // of tiles (whole z-slabs) so neighbouring rows share that XCD's L2.
+    const int wg = blockIdx.x;
+    const int L = (wg & 7) * p.tiles_per_xcd + (wg >> 3);
+    if (L >= p.n_tiles) return;  // uniform for the block
+
+    const int txl = p.tx_log2;
+    const int TX = 1 << txl, TY = 256 >> txl;
+    const int tix = L % p.tiles_x;
+    const int rem = L / p.tiles_x;
+    const int tiy = rem % p.tiles_y;
+    const int z = rem / p.tiles_y;
+    const int lx = threadIdx.x & (TX - 1), ly = threadIdx.x >> txl;
+    const int x0 = tix << txl, y0 = tiy * TY;
+    const int x = x0 + lx, y = y0 + ly;
+    const int nx = p.nx, ny = p.ny, nz = p.nz;
+    const bool active = (x < nx) && (y < ny);
+
+    int tag = p.uniform_tag;
+    uint32_t wall = 0;  // bit i: node x + c_i is not fluid
+    __shared__ uint8_t s_tag[TAGGED ? kTileBytes : 1];
+    const int WX = TX + 2, WY = TY + 2;
+    const int cidx = (WY + ly + 1) * WX + lx + 1;
+    if constexpr (TAGGED) {
+        const int total = WX * WY * 3;
+        for (int k = threadIdx.x; k < total; k += 256) {
+            const int ax = k % WX;
+            const int r = k / WX;
+            const int ay = r % WY;
+            const int az = r / WY;
+            const int gx = wrap_idx(x0 + ax - 1, nx);
+            const int gy = wrap_idx(y0 + ay - 1, ny);
+            const int gz = wrap_idx(z + az - 1, nz);
+            s_tag[k] = p.tags[((long long)gz * ny + gy) * nx + gx];
+        }
+        __syncthreads();
+        tag = s_tag[cidx];
+        sfor<Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            if constexpr (i > 0) {
+                using Vi = V<Q, i>;
+                const int t = s_tag[cidx + (Vi::z * WY + Vi::y) * WX + Vi::x];
+                if (!is_fluid_tag(t)) wall |= 1u << i;
+            }
+        });
+    }
+    const bool live = active && (!TAGGED || is_fluid_tag(tag));
+
+    // Neighbour offsets with periodic wrap; index 1 + c for c in {-1, 0, 1}.
+    const int xc = active ? x : 0, yc = active ? y : 0;
+    const int xo[3] = {xc == 0 ? nx - 1 : xc - 1, xc, xc + 1 == nx ? 0 : xc + 1};
+    const int yo[3] = {(yc == 0 ? ny - 1 : yc - 1) * nx, yc * nx, (yc + 1 == ny ? 0 : yc + 1) * nx};
+    const int nxy = nx * ny;
+    const int zo[3] = {(z == 0 ? nz - 1 : z - 1) * nxy, z * nxy, (z + 1 == nz ? 0 : z + 1) * nxy};
+    const int n = zo[1] + yo[1] + xo[1];
+    const long long st = p.stride;
+    S *__restrict__ f = static_cast<S *>(p.pops);
+
+    // ---- pull the node's populations
+    C h[Q];
+    if (live) {
+        sfor<Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            using Vi = V<Q, i>;
+            long long off;
+            if constexpr (PARITY == 0 || i == 0) {
+                off = (long long)i * st + n;
+            } else {
+                const int src = zo[1 - Vi::z] + yo[1 - Vi::y] + xo[1 - Vi::x];
+                const long long o_nb = (long long)Vi::opp * st + src;
+                if constexpr (TAGGED) {
+                    const bool wb = (wall >> Vi::opp) & 1u;
+                    off = wb ? (long long)i * st + n : o_nb;
+                } else {
+                    off = o_nb;
+                }
+            }
+            h[i] = (C)f[off];
+        });
+    } else {
+        sfor<Q>([&](auto I) { h[decltype(I)::value] = C(0); });
+    }
+
+    // ---- FP64 reductions of the loaded (time-t) state
+    double red[NRED];
+    if constexpr (MODE != MODE_STEP) {
+        double dr = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+        sfor<Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            using Vi = V<Q, i>;
+            const double v = (double)h[i];
+            dr += v;
+            if constexpr (Vi::x != 0) jx += Vi::x * v;
+            if constexpr (Vi::y != 0) jy += Vi::y * v;
+            if constexpr (Vi::z != 0) jz += Vi::z * v;
+        });
+        const double rho = p.rho0 + dr;
+        const double px = jx + 0.5 * p.force[0], py = jy + 0.5 * p.force[1], pz = jz + 0.5 * p.force[2];
+        const double ux = px / rho, uy = py / rho, uz = pz / rho;
+        const double uu = ux * ux + uy * uy + uz * uz;
+        const bool ok = isfinite(rho) && isfinite(uu);
+        const bool use = live && ok;
+        red[0] = use ? dr : 0.0;
+        red[1] = use ? px : 0.0;
+        red[2] = use ? py : 0.0;
+        red[3] = use ? pz : 0.0;
+        red[4] = use ? ux : 0.0;
+        red[5] = use ? uy : 0.0;
+        red[6] = use ? uz : 0.0;
+        red[7] = use ? 0.5 * uu : 0.0;
+        red[8] = use ? 0.5 * rho * uu : 0.0;
+        red[9] = (live && !ok) ? 1.0 : 0.0;
+    }
+
+    if constexpr (MODE != MODE_REDUCE) {
+        // ---- moments
+        C drho = C(0), jx = C(0), jy = C(0), jz = C(0);
+        sfor<Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            using Vi = V<Q, i>;
+            drho += h[i];
+            if constexpr (Vi::x == 1) jx += h[i];
+            if constexpr (Vi::x == -1) jx -= h[i];
+            if constexpr (Vi::y == 1) jy += h[i];
+            if constexpr (Vi::y == -1) jy -= h[i];
+            if constexpr (Vi::z == 1) jz += h[i];
+            if constexpr (Vi::z == -1) jz -= h[i];
+        });
+        const C Fx = (C)p.force[0], Fy = (C)p.force[1], Fz = (C)p.force[2];
+        const C rho = (C)p.rho0 + drho;
+        const C inv_rho = C(1) / rho;
+        const C ux = (jx + C(0.5) * Fx) * inv_rho;
+        const C uy = (jy + C(0.5) * Fy) * inv_rho;
+        const C uz = (jz + C(0.5) * Fz) * inv_rho;
+        const C uu = ux * ux + uy * uy + uz * uz;
+        const C uF = ux * Fx + uy * Fy + uz * Fz;
+
+        // ---- equilibrium, even/odd parts per pair k = 1..H (direction k, opp k+H)
+        C ev[H + 1], od[H + 1], cuk[H + 1];
+        ev[0] = C(V<Q, 0>::w) * (drho - C(1.5) * rho * uu);
+        od[0] = C(0);
+        cuk[0] = C(0);
+        sfor<H>([&](auto K) {
+            constexpr int k = decltype(K)::value + 1;
+            using Vk = V<Q, k>;
+            C cu = C(0);
+            if constexpr (Vk::x != 0) cu += C(Vk::x) * ux;
+            if constexpr (Vk::y != 0) cu += C(Vk::y) * uy;
+            if constexpr (Vk::z != 0) cu += C(Vk::z) * uz;
+            cuk[k] = cu;
+            ev[k] = C(Vk::w) * (drho + rho * (C(4.5) * cu * cu - C(1.5) * uu));
+            od[k] = C(Vk::w) * C(3) * rho * cu;
+        });
+
+        // ---- relaxation rates from the node's model
+        C wp = (C)p.omega, wm = (C)p.omega;
+        if constexpr ((MS & MS_TRT) != 0) {
+            if (tag == LBM_TAG_TRT) wm = (C)p.omega_minus;
+        }
+        if constexpr ((MS & (MS_SMAG | MS_MLP)) != 0) {
+            // Non-equilibrium momentum flux Pi_ab = sum c_a c_b (h - heq): only
+            // even parts contribute, 2 sum_k c_a c_b (h+_k - ev_k).
+            C pxx = C(0), pyy = C(0), pzz = C(0), pxy = C(0), pxz = C(0), pyz = C(0);
+            sfor<H>([&](auto K) {
+                constexpr int k = decltype(K)::value + 1;
+                using Vk = V<Q, k>;
+                const C ne = (h[k] + h[k + H]) - C(2) * ev[k];
+                if constexpr (Vk::x != 0) pxx += ne;
+                if constexpr (Vk::y != 0) pyy += ne;
+                if constexpr (Vk::z != 0) pzz += ne;
+                if constexpr (Vk::x * Vk::y != 0) pxy += C(Vk::x * Vk::y) * ne;
+                if constexpr (Vk::x * Vk::z != 0) pxz += C(Vk::x * Vk::z) * ne;
+                if constexpr (Vk::y * Vk::z != 0) pyz += C(Vk::y * Vk::z) * ne;
+            });
+            const C qn = sqrt(pxx * pxx + pyy * pyy + pzz * pzz + C(2) * (pxy * pxy + pxz * pxz + pyz * pyz));
+            const C tau0 = (C)p.tau;
+            const C tau_s = C(0.5) * (tau0 + sqrt(tau0 * tau0 + (C)p.smag_c * qn * inv_rho));
+            C tau_eff = tau_s;
+            if constexpr ((MS & MS_MLP) != 0) {
+                const bool want = live && tag == LBM_TAG_BGK_MLP;
+                if (p.has_mlp && __any(want)) {
+                    const float feat[7] = {(float)pxx, (float)pyy, (float)pzz, (float)pxy,
+                                           (float)pxz, (float)pyz, (float)rho};
+                    const float sp = mlp_wave_eval(p.mlp, feat);
+                    const C nu0 = (C)p.nu0;
+                    const C nut = nu0 * (C)sp;
+                    if (isfinite(nut) && nut <= C(10) * nu0) {
+                        if (tag == LBM_TAG_BGK_MLP) tau_eff = C(3) * (nu0 + nut) + C(0.5);
+                    }
+                }
+            }
+            if (tag == LBM_TAG_BGK_SMAG || tag == LBM_TAG_BGK_MLP) {
+                wp = C(1) / tau_eff;
+                wm = wp;
+            }
+        }
+
+        // ---- collide (pair form) and push
+        C hs[Q];
+        {
+            const C gp = C(1) - C(0.5) * wp, gm = C(1) - C(0.5) * wm;
+            const C F0 = C(V<Q, 0>::w) * C(-3) * uF;
+            hs[0] = h[0] - wp * (h[0] - ev[0]) + gp * F0;
+            sfor<H>([&](auto K) {
+                constexpr int k = decltype(K)::value + 1;
+                using Vk = V<Q, k>;
+                C cF = C(0);
+                if constexpr (Vk::x != 0) cF += C(Vk::x) * Fx;
+                if constexpr (Vk::y != 0) cF += C(Vk::y) * Fy;
+                if constexpr (Vk::z != 0) cF += C(Vk::z) * Fz;
+                const C Fe = C(Vk::w) * (C(9) * cuk[k] * cF - C(3) * uF);
+                const C Fo = C(Vk::w) * C(3) * cF;
+                const C hp = C(0.5) * (h[k] + h[k + H]);
+                const C hm = C(0.5) * (h[k] - h[k + H]);
+                const C A = gp * Fe - wp * (hp - ev[k]);
+                const C B = gm * Fo - wm * (hm - od[k]);
+                hs[k] = h[k] + A + B;
+                hs[k + H] = h[k + H] + A - B;
+            });
+        }
+
+        if (live) {
+            sfor<Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                using Vi = V<Q, i>;
+                C v = hs[i];
+                long long off;
+                if constexpr (i == 0) {
+                    off = n;
+                } else if constexpr (PARITY == 0) {
+                    off = (long long)Vi::opp * st + n;
+                } else {
+                    const int dst = zo[1 + Vi::z] + yo[1 + Vi::y] + xo[1 + Vi::x];
+                    off = (long long)i * st + dst;
+                    if constexpr (TAGGED) {
+                        if ((wall >> i) & 1u) off = (long long)Vi::opp * st + n;
+                    }
+                }
+                if constexpr (TAGGED) {
+                    if ((wall >> i) & 1u) {
+                        const int t = s_tag[cidx + (Vi::z * WY + Vi::y) * WX + Vi::x];
+                        if (t >= LBM_TAG_WALL0) {
+                            const double *uw = p.wall_u + 3 * (t - LBM_TAG_WALL0);
+                            C cu = C(0);
+                            if constexpr (Vi::x != 0) cu += C(Vi::x) * (C)uw[0];
+                            if constexpr (Vi::y != 0) cu += C(Vi::y) * (C)uw[1];
+                            if constexpr (Vi::z != 0) cu += C(Vi::z) * (C)uw[2];
+                            v -= C(6.0 * Vi::w) * (C)p.rho0 * cu;
+                        }
+                    }
+                }
+                f[off] = (S)v;
+            });
+        }
+    }
+
+    // ---- per-tile reduction partials (fixed order: shuffle tree, then waves 0..3)
+    if constexpr (MODE != MODE_STEP) {
+        __shared__ double s_red[4][NRED];
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+        for (int k = 0; k < NRED; ++k) {
+            double v = red[k];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+            if (lane == 0) s_red[wave][k] = v;
+        }
+        __syncthreads();
+        if (threadIdx.x < NRED) {
+            const int k = threadIdx.x;
+            p.partials[(long long)L * NRED + k] = (s_red[0][k] + s_red[1][k]) + (s_red[2][k] + s_red[3][k]);
+        }
+    }
+}
+
+// ------------------------------------------------------------- helpers
+
+// Equilibrium initialisation (FP64 arithmetic, rounded once to storage).
+template <int Q, int P>
+__global__ __launch_bounds__(256) void k_init(AuxParams a) {
+    using S = typename Prec<P>::S;
+    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= a.count) return;
+    const long long n = a.cell0 + t;
+    if (!is_fluid_tag(a.tags[n])) return;
+    const double rho = a.in_rho ? a.in_rho[t] : a.rho0;
+    const double ux = a.in_u ? a.in_u[t] : 0.0;
+    const double uy = a.in_u ? a.in_u[a.count + t] : 0.0;
+    const double uz = a.in_u ? a.in_u[2 * a.count + t] : 0.0;
+    const double drho = rho - a.rho0;
+    const double uu = ux * ux + uy * uy + uz * uz;
+    S *f = static_cast<S *>(a.pops);
+    sfor<Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        using Vi = V<Q, i>;
+        const double cu = Vi::x * ux + Vi::y * uy + Vi::z * uz;
+        const double heq = Vi::w * (drho + rho * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
+        f[(long long)i * a.stride + n] = (S)heq;
+    });
+}
+
+// Natural state of node n: h_i(n) for every i (slot map of the layout parity).
+template <int Q, int P>
+__device__ __forceinline__ void load_natural(const AuxParams &a, long long n, double (&fo)[Q]) {
+    using S = typename Prec<P>::S;
+    const S *f = static_cast<const S *>(a.pops);
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int x = (int)(n % nx), y = (int)((n / nx) % ny), z = (int)(n / ((long long)nx * ny));
+    sfor<Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        using Vi = V<Q, i>;
+        long long off = (long long)i * a.stride + n;
+        if (a.parity != 0 && i != 0) {
+            const int sx = wrap_idx(x - Vi::x, nx), sy = wrap_idx(y - Vi::y, ny), sz = wrap_idx(z - Vi::z, nz);
+            const long long src = ((long long)sz * ny + sy) * nx + sx;
+            if (is_fluid_tag(a.tags[src])) off = (long long)Vi::opp * a.stride + src;
+        }
+        fo[i] = (double)f[off] + Vi::w * a.rho0;
+    });
+}
+
+template <int Q, int P>
+__global__ __launch_bounds__(256) void k_gather(AuxParams a, int gmode) {
+    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= a.count) return;
+    const long long n = gmode == G_CELLS ? a.cells[t] : a.cell0 + t;
+    const bool fl = is_fluid_tag(a.tags[n]);
+    double fo[Q];
+    if (fl) {
+        load_natural<Q, P>(a, n, fo);
+    } else {
+        sfor<Q>([&](auto I) { fo[decltype(I)::value] = 0.0; });
+    }
+    if (gmode == G_POPS) {
+        sfor<Q>([&](auto I) { a.out[(long long)decltype(I)::value * a.count + t] = fo[decltype(I)::value]; });
+    } else if (gmode == G_CELLS) {
+        sfor<Q>([&](auto I) { a.out[t * Q + decltype(I)::value] = fo[decltype(I)::value]; });
+    } else {
+        double rho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+        sfor<Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            using Vi = V<Q, i>;
+            rho += fo[i];
+            jx += Vi::x * fo[i];
+            jy += Vi::y * fo[i];
+            jz += Vi::z * fo[i];
+        });
+        const double inv = fl ? 1.0 / rho : 0.0;
+        a.out[t] = rho;
+        a.out[a.count + t] = fl ? (jx + 0.5 * a.force[0]) * inv : 0.0;
+        a.out[2 * a.count + t] = fl ? (jy + 0.5 * a.force[1]) * inv : 0.0;
+        a.out[3 * a.count + t] = fl ? (jz + 0.5 * a.force[2]) * inv : 0.0;
+    }
+}
+
+// Write natural-layout populations (unshifted FP64 in, shifted storage out).
+template <int Q, int P>
+__global__ __launch_bounds__(256) void k_scatter(AuxParams a) {
+    using S = typename Prec<P>::S;
+    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= a.count) return;
+    const long long n = a.cell0 + t;
+    if (!is_fluid_tag(a.tags[n])) return;
+    S *f = static_cast<S *>(a.pops);
+    sfor<Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        using Vi = V<Q, i>;
+        f[(long long)i * a.stride + n] = (S)(a.in_f[(long long)i * a.count + t] - Vi::w * a.rho0);
+    });
+}
+
+// ------------------------------------------------------------- launchers
+
+template <int Q, int P, int MS, bool TG, int MODE>
+static hipError_t launch_step_par(const StepParams &p, int parity, hipStream_t s) {
+    const dim3 grid(8 * p.tiles_per_xcd), block(256);
+    if (parity == 0)
+        k_collide_stream<Q, P, MS, TG, MODE, 0><<<grid, block, 0, s>>>(p);
+    else
+        k_collide_stream<Q, P, MS, TG, MODE, 1><<<grid, block, 0, s>>>(p);
+    return hipGetLastError();
+}
+
+template <int Q, int P, int MS, bool TG>
+static hipError_t launch_step_mode(const StepParams &p, int mode, int parity, hipStream_t s) {
+    switch (mode) {
+        case MODE_STEP: return launch_step_par<Q, P, MS, TG, MODE_STEP>(p, parity, s);
+        case MODE_STEP_REDUCE: return launch_step_par<Q, P, MS, TG, MODE_STEP_REDUCE>(p, parity, s);
+        default: return launch_step_par<Q, P, MS_BGK, TG, MODE_REDUCE>(p, parity, s);
+    }
+}
+
+template <int Q, int P, int MS>
+static hipError_t launch_step_geo(const StepParams &p, bool tagged, int mode, int parity, hipStream_t s) {
+    return tagged ? launch_step_mode<Q, P, MS, true>(p, mode, parity, s)
+                  : launch_step_mode<Q, P, MS, false>(p, mode, parity, s);
+}
+
+template <int Q, int P>
+hipError_t launch_step(const StepParams &p, int ms, bool tagged, int mode, int parity, hipStream_t s) {
+    switch (ms) {
+        case MS_BGK: return launch_step_geo<Q, P, MS_BGK>(p, tagged, mode, parity, s);
+        case MS_TRT: return launch_step_geo<Q, P, MS_TRT>(p, tagged, mode, parity, s);
+        case MS_BGK | MS_SMAG: return launch_step_geo<Q, P, MS_BGK | MS_SMAG>(p, tagged, mode, parity, s);
+        case MS_BGK | MS_SMAG | MS_MLP:
+            return launch_step_geo<Q, P, MS_BGK | MS_SMAG | MS_MLP>(p, tagged, mode, parity, s);
+        case MS_BGK | MS_TRT | MS_SMAG | MS_MLP:
+            return launch_step_geo<Q, P, MS_BGK | MS_TRT | MS_SMAG | MS_MLP>(p, tagged, mode, parity, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int Q, int P>
+hipError_t launch_init(const AuxParams &a, hipStream_t s) {
+    const unsigned blocks = (unsigned)((a.count + 255) / 256);
+    k_init<Q, P><<<blocks, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+template <int Q, int P>
+hipError_t launch_gather(const AuxParams &a, int gmode, hipStream_t s) {
+    const unsigned blocks = (unsigned)((a.count + 255) / 256);
+    k_gather<Q, P><<<blocks, 256, 0, s>>>(a, gmode);
+    return hipGetLastError();
+}
+
+template <int Q, int P>
+hipError_t launch_scatter(const AuxParams &a, hipStream_t s) {
+    const unsigned blocks = (unsigned)((a.count + 255) / 256);
+    k_scatter<Q, P><<<blocks, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+#define LBMD_INSTANTIATE(Q, P)                                                                           \
+    template hipError_t launch_step<Q, P>(const StepParams &, int, bool, int, int, hipStream_t);          \
+    template hipError_t launch_init<Q, P>(const AuxParams &, hipStream_t);                                \
+    template hipError_t launch_gather<Q, P>(const AuxParams &, int, hipStream_t);                         \
+    template hipError_t launch_scatter<Q, P>(const AuxParams &, hipStream_t);
+
+}  // namespace lbmd

@@ -1,0 +1,292 @@
+"""Thin Python binding of the C ABI in include/lbm.h (argument marshalling only).
+
+Every function here forwards to the HIP library ``liblbm_hip.so`` built in this
+directory; all lattice arithmetic runs in its kernels.  If the library is
+missing, loading raises -- there is no CPU fallback.  torch supplies device
+buffers and the HIP stream handle only.
+
+Module-level functions keep the C names (``lbm_create``, ``lbm_step``, ...);
+:class:`Lattice` bundles them for convenience.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbm_hip.so")
+
+LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EHIP, LBM_EUNSTABLE, LBM_EUNSUPPORTED, LBM_ESTATE = 0, -1, -2, -3, -4, -5, -6
+LBM_F64, LBM_F32, LBM_F16S = 0, 1, 2
+TAG_SOLID, TAG_BGK, TAG_TRT, TAG_SMAG, TAG_MLP, TAG_WALL0 = 0, 1, 2, 3, 4, 16
+MLP_NPARAMS = 1359
+PREC_NAMES = {"f64": LBM_F64, "f32": LBM_F32, "f16s": LBM_F16S}
+PREC_BYTES = {LBM_F64: 8, LBM_F32: 4, LBM_F16S: 2}
+
+
+class LbmConfig(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("q", C.c_int32),
+                ("prec", C.c_int32), ("flags", C.c_int32), ("rho0", C.c_double), ("tau", C.c_double),
+                ("trt_lambda", C.c_double), ("smag_cs", C.c_double), ("force", C.c_double * 3),
+                ("wall_velocity", (C.c_double * 3) * 16)]
+
+
+class LbmMoments(C.Structure):
+    _fields_ = [("step", C.c_int64), ("n_fluid", C.c_int64), ("n_nonfinite", C.c_int64),
+                ("mass", C.c_double), ("mass_delta", C.c_double), ("momentum", C.c_double * 3),
+                ("velocity_sum", C.c_double * 3), ("kinetic_energy", C.c_double),
+                ("kinetic_energy_rho", C.c_double)]
+
+    def as_dict(self):
+        return {"step": self.step, "n_fluid": self.n_fluid, "n_nonfinite": self.n_nonfinite,
+                "mass": self.mass, "mass_delta": self.mass_delta, "momentum": np.array(self.momentum[:]),
+                "velocity_sum": np.array(self.velocity_sum[:]), "kinetic_energy": self.kinetic_energy,
+                "kinetic_energy_rho": self.kinetic_energy_rho}
+
+
+# Every symbol of include/lbm.h with its ctypes signature.
+_P = C.c_void_p
+SIGNATURES = {
+    "lbm_population_bytes": (C.c_size_t, [C.POINTER(LbmConfig)]),
+    "lbm_create": (C.c_int, [C.POINTER(LbmConfig), _P, _P, C.POINTER(_P)]),
+    "lbm_create_on_buffer": (C.c_int, [C.POINTER(LbmConfig), _P, _P, C.c_size_t, _P, C.POINTER(_P)]),
+    "lbm_destroy": (None, [_P]),
+    "lbm_set_launch": (C.c_int, [_P, C.c_int, C.c_int]),
+    "lbm_init_equilibrium": (C.c_int, [_P, _P, _P]),
+    "lbm_step": (C.c_int, [_P, C.c_int64]),
+    "lbm_step_reduce": (C.c_int, [_P, C.c_int64, C.c_int64, C.POINTER(LbmMoments), C.c_int64]),
+    "lbm_reduce": (C.c_int, [_P, C.POINTER(LbmMoments)]),
+    "lbm_synchronize": (C.c_int, [_P]),
+    "lbm_time": (C.c_int64, [_P]),
+    "lbm_read_fields": (C.c_int, [_P, _P, _P]),
+    "lbm_read_populations": (C.c_int, [_P, _P]),
+    "lbm_read_cells": (C.c_int, [_P, _P, C.c_int64, _P]),
+    "lbm_write_populations": (C.c_int, [_P, _P, C.c_int64]),
+    "lbm_set_mlp": (C.c_int, [_P, _P, C.c_size_t]),
+    "lbm_mlp_infer": (C.c_int, [_P, C.c_double, _P, C.c_int64, _P, _P]),
+    "lbm_filter_snapshot": (C.c_int, [_P, C.c_int, _P, _P]),
+    "lbm_mlp_grad": (C.c_int, [_P, _P, _P, C.c_int64, _P, _P, _P]),
+    "lbm_mlp_train": (C.c_int, [_P, _P, _P, C.c_int64, _P, C.c_int, C.c_int, C.c_double, _P, _P]),
+    "lbm_velocity": (C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_double)]),
+    "lbm_last_error": (C.c_char_p, []),
+    "lbm_variant_name": (C.c_char_p, [_P]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} missing "
+                               "(run __graft_entry__.build() or python paper_2506_09242_amd/build.py)")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+class LbmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"lbm status {status}: {msg}")
+        self.status = status
+
+
+def _check(rc):
+    if rc != LBM_OK:
+        raise LbmError(rc, lib().lbm_last_error().decode())
+    return rc
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _dev(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def make_config(nx, ny, nz, q=19, prec=LBM_F64, tau=0.8, rho0=1.0, trt_lambda=3.0 / 16.0, smag_cs=0.0,
+                force=(0.0, 0.0, 0.0), wall_velocity: Optional[Sequence] = None) -> LbmConfig:
+    if isinstance(prec, str):
+        prec = PREC_NAMES[prec]
+    c = LbmConfig()
+    c.nx, c.ny, c.nz, c.q, c.prec, c.flags = nx, ny, nz, q, prec, 0
+    c.rho0, c.tau, c.trt_lambda, c.smag_cs = rho0, tau, trt_lambda, smag_cs
+    for a in range(3):
+        c.force[a] = force[a]
+    if wall_velocity is not None:
+        for k, v in enumerate(wall_velocity):
+            for a in range(3):
+                c.wall_velocity[k][a] = v[a]
+    return c
+
+
+# --------------------------------------------------------- C-named wrappers
+def lbm_population_bytes(cfg: LbmConfig) -> int:
+    return lib().lbm_population_bytes(C.byref(cfg))
+
+
+def lbm_velocity(q, i):
+    c = (C.c_int * 3)()
+    w = C.c_double()
+    o = lib().lbm_velocity(q, i, c, C.byref(w))
+    if o < 0:
+        raise ValueError("bad velocity index")
+    return (c[0], c[1], c[2]), w.value, o
+
+
+def lbm_last_error() -> str:
+    return lib().lbm_last_error().decode()
+
+
+def lbm_mlp_infer(params: np.ndarray, nu0: float, feat_dev, nut_dev, stream=None):
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    n = feat_dev.shape[0]
+    _check(lib().lbm_mlp_infer(_ptr(p), nu0, _dev(feat_dev), n, _dev(nut_dev), _stream_handle(stream)))
+
+
+def lbm_mlp_grad(params_dev, feat_dev, target_dev, grad_dev, loss_dev, stream=None):
+    _check(lib().lbm_mlp_grad(_dev(params_dev), _dev(feat_dev), _dev(target_dev), feat_dev.shape[0],
+                              _dev(grad_dev), _dev(loss_dev), _stream_handle(stream)))
+
+
+def lbm_mlp_train(params_dev, feat_dev, target_dev, perm_dev, batch, epochs, lr, loss_log_dev, stream=None):
+    _check(lib().lbm_mlp_train(_dev(params_dev), _dev(feat_dev), _dev(target_dev), feat_dev.shape[0],
+                               _dev(perm_dev), batch, epochs, lr, _dev(loss_log_dev), _stream_handle(stream)))
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+class Lattice:
+    """One lattice on the current GPU (owner of an ``lbm_lattice*``)."""
+
+    def __init__(self, tags: np.ndarray, q=19, prec=LBM_F64, tau=0.8, rho0=1.0, trt_lambda=3.0 / 16.0,
+                 smag_cs=0.0, force=(0.0, 0.0, 0.0), wall_velocity=None, stream=None, torch_buffer=False):
+        tags = np.ascontiguousarray(tags, dtype=np.uint8)
+        assert tags.ndim == 3
+        nz, ny, nx = tags.shape
+        self.shape = (nz, ny, nx)
+        self.N = nx * ny * nz
+        self.q = q
+        self.cfg = make_config(nx, ny, nz, q, prec, tau, rho0, trt_lambda, smag_cs, force, wall_velocity)
+        self.tags = tags
+        self._stream = _stream_handle(stream)
+        self._buf = None
+        h = C.c_void_p()
+        if torch_buffer:
+            import torch
+            nbytes = lbm_population_bytes(self.cfg)
+            if nbytes == 0:
+                _check(LBM_EINVAL)
+            self._buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+            _check(lib().lbm_create_on_buffer(C.byref(self.cfg), _ptr(tags), _dev(self._buf), nbytes,
+                                              self._stream, C.byref(h)))
+        else:
+            _check(lib().lbm_create(C.byref(self.cfg), _ptr(tags), self._stream, C.byref(h)))
+        self.h = h
+
+    # lifecycle
+    def close(self):
+        if self.h:
+            lib().lbm_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def variant(self) -> str:
+        return lib().lbm_variant_name(self.h).decode()
+
+    @property
+    def time(self) -> int:
+        return lib().lbm_time(self.h)
+
+    @property
+    def stream_handle(self) -> int:
+        return self._stream.value or 0
+
+    def set_launch(self, tx, ty):
+        _check(lib().lbm_set_launch(self.h, tx, ty))
+
+    def init_equilibrium(self, rho=None, u=None):
+        r = None if rho is None else np.ascontiguousarray(rho, dtype=np.float64).reshape(self.N)
+        v = None if u is None else np.ascontiguousarray(u, dtype=np.float64).reshape(3 * self.N)
+        _check(lib().lbm_init_equilibrium(self.h, None if r is None else _ptr(r), None if v is None else _ptr(v)))
+
+    def step(self, n):
+        _check(lib().lbm_step(self.h, int(n)))
+
+    def step_reduce(self, n, every):
+        ns = int(n) // int(every) + 1
+        arr = (LbmMoments * ns)()
+        rc = lib().lbm_step_reduce(self.h, int(n), int(every), arr, ns)
+        series = [m.as_dict() for m in arr]
+        if rc == LBM_EUNSTABLE:
+            raise LbmError(rc, lbm_last_error())
+        _check(rc)
+        return series
+
+    def reduce(self):
+        m = LbmMoments()
+        rc = lib().lbm_reduce(self.h, C.byref(m))
+        if rc == LBM_EUNSTABLE:
+            raise LbmError(rc, lbm_last_error())
+        _check(rc)
+        return m.as_dict()
+
+    def synchronize(self):
+        _check(lib().lbm_synchronize(self.h))
+
+    def read_fields(self):
+        rho = np.empty(self.shape)
+        u = np.empty((3,) + self.shape)
+        _check(lib().lbm_read_fields(self.h, _ptr(rho), _ptr(u)))
+        return rho, u
+
+    def read_populations(self):
+        f = np.empty((self.q,) + self.shape)
+        _check(lib().lbm_read_populations(self.h, _ptr(f)))
+        return f
+
+    def read_cells(self, cells):
+        c = np.ascontiguousarray(cells, dtype=np.int64)
+        f = np.empty((c.size, self.q))
+        _check(lib().lbm_read_cells(self.h, _ptr(c), c.size, _ptr(f)))
+        return f
+
+    def write_populations(self, f, t=0):
+        a = np.ascontiguousarray(f, dtype=np.float64).reshape(self.q * self.N)
+        _check(lib().lbm_write_populations(self.h, _ptr(a), int(t)))
+
+    def set_mlp(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        _check(lib().lbm_set_mlp(self.h, _ptr(p), p.size))
+
+    def filter_snapshot(self, factor, feat_dev, target_dev):
+        _check(lib().lbm_filter_snapshot(self.h, int(factor), _dev(feat_dev), _dev(target_dev)))

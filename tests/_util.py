@@ -1,0 +1,40 @@
+"""Shared helpers of the GPU tests: run the HIP path and the oracle on the same
+seeded inputs and compare what is unique (fluid-node populations)."""
+import numpy as np
+
+import oracle
+from paper_2506_09242_amd import lbm
+
+FLUID = (1, 2, 3, 4)
+
+
+def fluid_mask(tags):
+    return np.isin(tags, FLUID)
+
+
+def make_pair(tags, q=19, prec=lbm.LBM_F64, rho=None, u=None, mlp=None, **kw):
+    """Oracle and HIP lattices with the same configuration and initial state."""
+    nz, ny, nx = tags.shape
+    o = oracle.Oracle(nx, ny, nz, q=q, tags=tags, mlp=mlp, **kw)
+    o.init_equilibrium(rho, u)
+    L = lbm.Lattice(tags, q=q, prec=prec, **kw)
+    if mlp is not None:
+        L.set_mlp(mlp)
+    L.init_equilibrium(rho, u)
+    return o, L
+
+
+def max_rel_pop_error(f_gpu, f_orc, tags):
+    m = fluid_mask(tags)
+    a = f_gpu[:, m]
+    b = f_orc[:, m]
+    return float(np.max(np.abs(a - b) / np.abs(b)))
+
+
+def max_abs_pop_error(f_gpu, f_orc, tags):
+    m = fluid_mask(tags)
+    return float(np.max(np.abs(f_gpu[:, m] - f_orc[:, m])))
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))

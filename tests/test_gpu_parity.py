@@ -1,0 +1,273 @@
+"""Parity of the HIP collide-and-stream path with the FP64 oracle (GPU).
+
+Bar: FP64 populations of every fluid node within 1e-12 relative of the
+oracle after N steps (both AA parities), reductions within 1e-12; launch
+geometry and checkpoint round trips bitwise-exact.  Reduced-precision paths
+are compared with the FP64 GPU path and their errors are stated.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2506_09242_amd import inputs, lbm
+
+from _util import fluid_mask, make_pair, max_abs_pop_error, max_rel_pop_error, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    lbm.lib()
+    yield
+
+
+def _print(*a):
+    print(*a, flush=True)
+
+
+# ------------------------------------------------------- Taylor-Green 32^3
+def test_tgv32_d3q19_bgk_fp64_full():
+    """D3Q19 BGK Taylor-Green 32^3, u0 = 0.04, Re = 100 with nu = u0 L / Re,
+    200 steps, FP64: every population of every node vs the oracle."""
+    n, u0, Re = 32, 0.04, 100.0
+    tau = 3.0 * u0 * n / Re + 0.5
+    rho, u = inputs.tgv3d_fields(n, u0)
+    tags = inputs.all_fluid(n, n, n)
+    o, L = make_pair(tags, q=19, tau=tau, rho=rho, u=u)
+    assert L.variant == "D3Q19/f64/bgk/uniform"
+    ser = L.step_reduce(200, 50)
+    o_ser = []
+    for k in range(5):
+        o_ser.append(o.moments())
+        if k < 4:
+            o.run(50)
+    f = L.read_populations()
+    err = max_rel_pop_error(f, o.f, tags)
+    _print("tgv32 max rel pop err", err)
+    assert err <= TOL
+    r_g, u_g = L.read_fields()
+    r_o, u_o = o.fields()
+    assert rel_l2(u_g, u_o) <= TOL and rel_l2(r_g, r_o) <= TOL
+    for s, m in zip(ser, o_ser):
+        assert abs(s["kinetic_energy"] * s["n_fluid"] - m["ke_sum"]) <= TOL * m["ke_sum"]
+        assert abs(s["kinetic_energy_rho"] - m["ke_rho_sum"]) <= TOL * m["ke_rho_sum"]
+        assert abs(s["mass_delta"] - m["mass_delta"]) <= TOL * n ** 3
+        assert np.allclose(s["momentum"], m["momentum"], rtol=0, atol=TOL * n ** 3 * u0)
+        assert np.allclose(s["velocity_sum"], m["sum_u"], rtol=0, atol=TOL * n ** 3 * u0)
+        assert s["n_nonfinite"] == 0
+
+
+# ---------------------------------------------------------------- cavity
+@pytest.mark.parametrize("steps", [150, 151])
+def test_cavity_d3q19_fp64(steps):
+    """Lid-driven cavity (solid shell, moving lid), ragged tile coverage."""
+    n = 26
+    tags = inputs.cavity_tags(n)
+    o, L = make_pair(tags, q=19, tau=0.6, wall_velocity=[(0.1, 0, 0)])
+    assert L.variant == "D3Q19/f64/bgk/tagged"
+    L.step(steps)
+    o.run(steps)
+    err = max_rel_pop_error(L.read_populations(), o.f, tags)
+    _print("cavity", steps, err)
+    assert err <= TOL
+    m = L.reduce()
+    mo = o.moments()
+    assert abs(m["mass_delta"] - mo["mass_delta"]) <= 1e-12 * m["mass"]
+    # components that vanish by symmetry are round-off on both sides: absolute
+    # scale = fluid nodes x lid speed
+    assert np.allclose(m["momentum"], mo["momentum"], rtol=1e-12, atol=1e-12 * m["n_fluid"] * 0.1)
+
+
+# ---------------------------------------------------------------- porous
+@pytest.mark.parametrize("q", [19, 27])
+def test_porous_trt_force_fp64(q):
+    """TRT (Lambda = 3/16) with a body force through a random solid, odd step count,
+    non-cubic ragged lattice."""
+    nx, ny, nz = 40, 22, 18
+    tags = inputs.random_tags(nx, ny, nz, seed=3, solid_frac=0.3, wall_frac=0.0, fluid_tags=(inputs.TAG_TRT,))
+    rho, u = inputs.random_fields(nx, ny, nz, seed=5)
+    o, L = make_pair(tags, q=q, tau=1.0, force=(1e-5, 2e-6, 0.0), rho=rho, u=u)
+    L.step(101)
+    o.run(101)
+    err = max_rel_pop_error(L.read_populations(), o.f, tags)
+    _print("porous", q, err)
+    assert err <= TOL
+
+
+@pytest.mark.parametrize("q", [19, 27])
+def test_mixed_models_and_walls_fp64(q):
+    """Every fluid model and two moving walls in one lattice (the all-model kernel)."""
+    nx, ny, nz = 37, 19, 11
+    tags = inputs.random_tags(nx, ny, nz, seed=11, solid_frac=0.15, wall_frac=0.1,
+                              fluid_tags=(inputs.TAG_BGK, inputs.TAG_TRT, inputs.TAG_SMAG))
+    rho, u = inputs.random_fields(nx, ny, nz, seed=12)
+    kw = dict(tau=0.7, smag_cs=0.15, force=(0.0, 1e-5, -1e-5), wall_velocity=[(0.05, 0, 0), (0, -0.04, 0.02)])
+    o, L = make_pair(tags, q=q, rho=rho, u=u, **kw)
+    assert L.variant.endswith("/all/tagged")
+    L.step(57)
+    o.run(57)
+    err = max_rel_pop_error(L.read_populations(), o.f, tags)
+    _print("mixed", q, err)
+    assert err <= TOL
+
+
+def test_tgv_d3q27_smagorinsky_fp64():
+    n = 24
+    rho, u = inputs.tgv3d_fields(n, 0.05)
+    tags = inputs.all_fluid(n, n, n, inputs.TAG_SMAG)
+    o, L = make_pair(tags, q=27, tau=0.505, smag_cs=0.1, rho=rho, u=u)
+    assert L.variant == "D3Q27/f64/bgk+smag/uniform"
+    L.step(120)
+    o.run(120)
+    err = max_rel_pop_error(L.read_populations(), o.f, tags)
+    _print("tgv27 smag", err)
+    assert err <= TOL
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 18), (3, 1, 5), (65, 2, 3), (300, 3, 2)])
+def test_degenerate_and_wide_shapes_fp64(shape):
+    """Single-node-wide axes (periodic self-neighbours), wide rows, few planes."""
+    nx, ny, nz = shape
+    tags = inputs.random_tags(nx, ny, nz, seed=nx * 7 + ny, solid_frac=0.2, wall_frac=0.1)
+    if not fluid_mask(tags).any():
+        tags[0, 0, 0] = inputs.TAG_BGK
+    rho, u = inputs.random_fields(nx, ny, nz, seed=2)
+    o, L = make_pair(tags, q=19, tau=0.9, rho=rho, u=u, wall_velocity=[(0.03, 0, 0), (0, 0, 0.02)])
+    L.step(33)
+    o.run(33)
+    assert max_rel_pop_error(L.read_populations(), o.f, tags) <= TOL
+
+
+def test_zero_steps_and_single_cell():
+    tags = np.zeros((3, 3, 3), np.uint8)
+    tags[1, 1, 1] = inputs.TAG_BGK
+    rho, u = inputs.random_fields(3, 3, 3, seed=1, du=0.05)
+    o, L = make_pair(tags, q=27, tau=0.75, rho=rho, u=u)
+    f0 = L.read_populations()
+    L.step(0)
+    assert np.array_equal(L.read_populations(), f0)
+    L.step(9)
+    o.run(9)
+    assert max_rel_pop_error(L.read_populations(), o.f, tags) <= TOL
+
+
+# ------------------------------------------------------- determinism (T6)
+@pytest.mark.parametrize("prec", [lbm.LBM_F64, lbm.LBM_F32, lbm.LBM_F16S])
+def test_launch_shape_is_bitwise_irrelevant(prec):
+    nx, ny, nz = 70, 21, 9
+    tags = inputs.random_tags(nx, ny, nz, seed=21, solid_frac=0.2, wall_frac=0.05)
+    rho, u = inputs.random_fields(nx, ny, nz, seed=22)
+    outs = []
+    for tx in (32, 64, 128, 256):
+        L = lbm.Lattice(tags, q=19, prec=prec, tau=0.8, wall_velocity=[(0.05, 0, 0), (0, 0.02, 0)])
+        L.set_launch(tx, 256 // tx)
+        L.init_equilibrium(rho, u)
+        L.step(13)
+        outs.append(L.read_populations())
+        L.close()
+    for f in outs[1:]:
+        assert np.array_equal(f, outs[0])
+
+
+def test_reductions_repeatable():
+    n = 40
+    rho, u = inputs.tgv3d_fields(n, 0.05)
+    L = lbm.Lattice(inputs.all_fluid(n, n, n), q=19, prec=lbm.LBM_F32, tau=0.6)
+    L.init_equilibrium(rho, u)
+    a = L.step_reduce(20, 5)
+    L.init_equilibrium(rho, u)
+    b = L.step_reduce(20, 5)
+    for x, y in zip(a, b):
+        assert x["kinetic_energy"] == y["kinetic_energy"] and x["mass_delta"] == y["mass_delta"]
+
+
+def test_fused_and_standalone_reductions_agree():
+    """The reduction fused into a step and the standalone pass see the same state."""
+    n = 20
+    tags = inputs.cavity_tags(n)
+    L = lbm.Lattice(tags, q=19, prec=lbm.LBM_F64, tau=0.6, wall_velocity=[(0.1, 0, 0)])
+    L.init_equilibrium()
+    L.step(7)
+    m_standalone = L.reduce()
+    ser = L.step_reduce(3, 3)  # sample at t=7 fused into the next step, t=10 standalone
+    assert ser[0]["step"] == 7 and ser[1]["step"] == 10
+    for k in ("mass_delta", "kinetic_energy", "kinetic_energy_rho"):
+        assert abs(ser[0][k] - m_standalone[k]) <= 1e-14 * max(1e-300, abs(m_standalone[k])) + 1e-18
+
+
+# --------------------------------------------------------- checkpoint (T11)
+@pytest.mark.parametrize("prec", [lbm.LBM_F64, lbm.LBM_F32])
+def test_checkpoint_roundtrip_bitwise(prec):
+    nx, ny, nz = 33, 17, 12
+    tags = inputs.random_tags(nx, ny, nz, seed=31, solid_frac=0.2, wall_frac=0.05)
+    rho, u = inputs.random_fields(nx, ny, nz, seed=32)
+    kw = dict(q=19, prec=prec, tau=0.7, wall_velocity=[(0.04, 0, 0), (0, 0, 0.03)])
+    A = lbm.Lattice(tags, **kw)
+    A.init_equilibrium(rho, u)
+    A.step(11)  # odd parity
+    ck = A.read_populations()
+    B = lbm.Lattice(tags, **kw)
+    B.write_populations(ck, t=A.time)
+    assert B.time == 11
+    A.step(8)
+    B.step(8)
+    assert np.array_equal(A.read_populations(), B.read_populations())
+
+
+def test_read_cells_matches_full_read():
+    nx, ny, nz = 29, 13, 7
+    tags = inputs.random_tags(nx, ny, nz, seed=41)
+    L = lbm.Lattice(tags, q=27, prec=lbm.LBM_F64, tau=0.7, wall_velocity=[(0.02, 0, 0), (0, 0, 0)])
+    rho, u = inputs.random_fields(nx, ny, nz, seed=42)
+    L.init_equilibrium(rho, u)
+    L.step(5)
+    f = L.read_populations().reshape(27, -1)
+    cells = np.array([0, 5, 100, nx * ny * nz - 1, 777])
+    assert np.array_equal(L.read_cells(cells), f[:, cells].T)
+
+
+def test_torch_owned_buffer():
+    n = 16
+    rho, u = inputs.tgv3d_fields(n, 0.04)
+    A = lbm.Lattice(inputs.all_fluid(n, n, n), q=19, tau=0.6)
+    B = lbm.Lattice(inputs.all_fluid(n, n, n), q=19, tau=0.6, torch_buffer=True)
+    for L in (A, B):
+        L.init_equilibrium(rho, u)
+        L.step(10)
+    assert np.array_equal(A.read_populations(), B.read_populations())
+
+
+def test_nonfinite_detection():
+    n = 8
+    L = lbm.Lattice(inputs.all_fluid(n, n, n), q=19, prec=lbm.LBM_F32, tau=0.6)
+    rho = np.ones((n, n, n))
+    rho[3, 3, 3] = np.nan
+    L.init_equilibrium(rho, None)
+    with pytest.raises(lbm.LbmError) as e:
+        L.reduce()
+    assert e.value.status == lbm.LBM_EUNSTABLE
+
+
+# ------------------------------------------------------ reduced precision
+@pytest.mark.parametrize("prec,bound", [(lbm.LBM_F32, 1e-4), (lbm.LBM_F16S, 3e-2)])
+def test_reduced_precision_error_is_stated(prec, bound):
+    """FP32-shifted and FP16-storage vs the FP64 GPU path on the 32^3 Taylor-Green
+    (200 steps): relative L2 velocity error printed; sanity bound only."""
+    n, u0 = 32, 0.04
+    tau = 3.0 * u0 * n / 100.0 + 0.5
+    rho, u = inputs.tgv3d_fields(n, u0)
+    res = {}
+    for p in (lbm.LBM_F64, prec):
+        L = lbm.Lattice(inputs.all_fluid(n, n, n), q=19, prec=p, tau=tau)
+        L.init_equilibrium(rho, u)
+        ser = L.step_reduce(200, 200)
+        res[p] = (L.read_fields()[1], ser[-1]["kinetic_energy"])
+    e_u = rel_l2(res[prec][0], res[lbm.LBM_F64][0])
+    e_k = abs(res[prec][1] / res[lbm.LBM_F64][1] - 1.0)
+    _print(f"precision {prec}: velocity rel L2 {e_u:.3e}, k rel err {e_k:.3e}")
+    assert e_u < bound and e_k < bound
