@@ -198,6 +198,19 @@ lbm_status lbm_read_cells(lbm_lattice *lat, const int64_t *cells_host, int64_t n
  * Synchronizes. */
 lbm_status lbm_write_populations(lbm_lattice *lat, const double *f_host, int64_t t);
 
+/* Checkpoint: the stored populations h_i = f_i - w_i rho0 of the natural
+ * state, widened exactly to FP64 (layout as lbm_read_populations; non-fluid
+ * nodes read 0).  Writing back what was read with lbm_write_state restores
+ * the lattice bit for bit in every storage precision (an unshifted round trip
+ * through lbm_read_populations is exact only for FP32/FP16 storage).
+ * Synchronizes. */
+lbm_status lbm_read_state(lbm_lattice *lat, double *h_host);
+
+/* Restore a state read by lbm_read_state and set the time counter to t.
+ * Values are rounded to the storage precision (exact for values that came
+ * from the same precision).  Synchronizes. */
+lbm_status lbm_write_state(lbm_lattice *lat, const double *h_host, int64_t t);
+
 /* --------------------------------------------------------- learned closure */
 
 /* Number of floats in a packed closure parameter vector. */

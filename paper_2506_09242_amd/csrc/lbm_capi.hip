@@ -42,7 +42,9 @@ struct lbm_lattice {
     bool own_pops = false;
     long long stride = 0;           // elements per slot
     long long ncell = 0;
-    double *d_partials = nullptr;   // [n_tiles][NRED]
+    double *d_partials = nullptr;   // [NRED][max_tiles]
+    long long max_tiles = 0;
+    double *d_stage1 = nullptr;     // [NRED][kFinalizeBlocks]
     double *d_series = nullptr;     // [series_cap][NRED]
     long long series_cap = 0;
     void *d_mlp = nullptr;          // packed closure block (lbm_mlp.hip)
@@ -166,6 +168,7 @@ StepParams step_params(const lbm_lattice *L) {
     p.tags = L->d_tags;
     p.wall_u = L->d_wall;
     p.partials = L->d_partials;
+    p.partial_stride = L->max_tiles;
     p.stride = L->stride;
     p.nx = c.nx;
     p.ny = c.ny;
@@ -220,32 +223,55 @@ struct DevBuf {
 
 // ---------------------------------------------------------- finalize kernel
 namespace lbmd {
-// Fixed-order sum of the per-tile partials: Neumaier per thread over a
-// strided subset, then a pairwise tree in LDS.
-__global__ __launch_bounds__(256) void k_finalize(const double *part, int nt, double *out) {
-    __shared__ double s[256];
+__device__ __forceinline__ void neumaier_add(double &sum, double &comp, double v) {
+    const double u = sum + v;
+    comp += (fabs(sum) >= fabs(v)) ? (sum - u) + v : (v - u) + sum;
+    sum = u;
+}
+
+// Pairwise tree over 256 LDS values (fixed order); result in s[0].
+__device__ __forceinline__ void lds_tree(double *s) {
     const int t = threadIdx.x;
+    for (int w = 128; w > 0; w >>= 1) {
+        __syncthreads();
+        if (t < w) s[t] += s[t + w];
+    }
+    __syncthreads();
+}
+
+// Stage 1: block b sums a contiguous run of tiles per slot (coalesced reads,
+// Neumaier per thread, pairwise tree across the block).
+__global__ __launch_bounds__(256) void k_finalize1(const double *part, long long pstride, int nt, int chunk,
+                                                   double *stage1) {
+    __shared__ double s[256];
+    const int t = threadIdx.x, b = blockIdx.x;
+    const int t0 = b * chunk, t1 = min(nt, t0 + chunk);
     for (int k = 0; k < NRED; ++k) {
         double sum = 0.0, comp = 0.0;
-        for (int b = t; b < nt; b += 256) {
-            const double v = part[(long long)b * NRED + k];
-            const double u = sum + v;
-            comp += (fabs(sum) >= fabs(v)) ? (sum - u) + v : (v - u) + sum;
-            sum = u;
-        }
+        for (int i = t0 + t; i < t1; i += 256) neumaier_add(sum, comp, part[(long long)k * pstride + i]);
         s[t] = sum + comp;
-        __syncthreads();
-        for (int w = 128; w > 0; w >>= 1) {
-            if (t < w) s[t] += s[t + w];
-            __syncthreads();
-        }
-        if (t == 0) out[k] = s[0];
-        __syncthreads();
+        lds_tree(s);
+        if (t == 0) stage1[k * kFinalizeBlocks + b] = s[0];
     }
 }
 
-hipError_t launch_finalize(const double *partials, int n_tiles, double *out, hipStream_t s) {
-    k_finalize<<<1, 256, 0, s>>>(partials, n_tiles, out);
+// Stage 2: one block sums the stage-1 results per slot.
+__global__ __launch_bounds__(256) void k_finalize2(const double *stage1, int nb, double *out) {
+    __shared__ double s[256];
+    const int t = threadIdx.x;
+    for (int k = 0; k < NRED; ++k) {
+        s[t] = t < nb ? stage1[k * kFinalizeBlocks + t] : 0.0;
+        lds_tree(s);
+        if (t == 0) out[k] = s[0];
+    }
+}
+
+hipError_t launch_finalize(const double *partials, long long partial_stride, int n_tiles, double *stage1, double *out,
+                           hipStream_t s) {
+    const int nb = std::min(kFinalizeBlocks, std::max(1, (n_tiles + 255) / 256));
+    const int chunk = (n_tiles + nb - 1) / nb;
+    k_finalize1<<<nb, 256, 0, s>>>(partials, partial_stride, n_tiles, chunk, stage1);
+    k_finalize2<<<1, 256, 0, s>>>(stage1, nb, out);
     return hipGetLastError();
 }
 }  // namespace lbmd
@@ -358,11 +384,18 @@ static lbm_status create_impl(const lbm_config *cfg, const uint8_t *tags_host, v
         const long long tx = 1LL << l, ty = 256 >> l;
         max_tiles = std::max(max_tiles, ((cfg->nx + tx - 1) / tx) * ((cfg->ny + ty - 1) / ty) * cfg->nz);
     }
+    L->max_tiles = max_tiles;
     e = hipMalloc(&L->d_partials, (size_t)max_tiles * NRED * sizeof(double));
     if (e != hipSuccess) {
         (void)hipGetLastError();
         L->d_partials = nullptr;
         return bail(set_err(LBM_ENOMEM, "hipMalloc of reduction partials failed"));
+    }
+    e = hipMalloc(&L->d_stage1, (size_t)kFinalizeBlocks * NRED * sizeof(double));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        L->d_stage1 = nullptr;
+        return bail(set_err(LBM_ENOMEM, "hipMalloc of reduction stage buffer failed"));
     }
     e = hipMemcpyAsync(L->d_tags, tags_host, (size_t)N, hipMemcpyHostToDevice, L->stream);
     if (e == hipSuccess)
@@ -393,6 +426,7 @@ extern "C" void lbm_destroy(lbm_lattice *lat) {
     if (lat->d_tags) (void)hipFree(lat->d_tags);
     if (lat->d_wall) (void)hipFree(lat->d_wall);
     if (lat->d_partials) (void)hipFree(lat->d_partials);
+    if (lat->d_stage1) (void)hipFree(lat->d_stage1);
     if (lat->d_series) (void)hipFree(lat->d_series);
     lbmd_free_mlp(lat);
     delete lat;
@@ -536,8 +570,8 @@ extern "C" lbm_status lbm_step_reduce(lbm_lattice *lat, int64_t n_steps, int64_t
         if (s % every == 0) {
             st = launch_one(lat, MODE_STEP_REDUCE);
             if (st != LBM_OK) return st;
-            HIPCHK(lat, launch_finalize(lat->d_partials, lat->n_tiles, lat->d_series + (s / every) * NRED,
-                                        lat->stream));
+            HIPCHK(lat, launch_finalize(lat->d_partials, lat->max_tiles, lat->n_tiles, lat->d_stage1,
+                                        lat->d_series + (s / every) * NRED, lat->stream));
         } else {
             st = launch_one(lat, MODE_STEP);
             if (st != LBM_OK) return st;
@@ -546,7 +580,8 @@ extern "C" lbm_status lbm_step_reduce(lbm_lattice *lat, int64_t n_steps, int64_t
     if (n_steps % every == 0) {
         st = launch_one(lat, MODE_REDUCE);
         if (st != LBM_OK) return st;
-        HIPCHK(lat, launch_finalize(lat->d_partials, lat->n_tiles, lat->d_series + (ns - 1) * NRED, lat->stream));
+        HIPCHK(lat, launch_finalize(lat->d_partials, lat->max_tiles, lat->n_tiles, lat->d_stage1,
+                                    lat->d_series + (ns - 1) * NRED, lat->stream));
     }
     std::vector<double> h((size_t)ns * NRED);
     HIPCHK(lat, hipMemcpyAsync(h.data(), lat->d_series, h.size() * sizeof(double), hipMemcpyDeviceToHost,
@@ -568,7 +603,7 @@ extern "C" lbm_status lbm_reduce(lbm_lattice *lat, lbm_moments *out) {
 }
 
 // ---------------------------------------------------------------- readback
-static lbm_status gather_range(lbm_lattice *lat, int gmode, double *host, int per_cell) {
+static lbm_status gather_range(lbm_lattice *lat, int gmode, double *host, int per_cell, int shifted) {
     const long long N = lat->ncell;
     const long long chunk = chunk_cells(lat, per_cell);
     DevBuf buf;
@@ -581,6 +616,7 @@ static lbm_status gather_range(lbm_lattice *lat, int gmode, double *host, int pe
         a.cell0 = c0;
         a.count = cnt;
         a.out = d;
+        a.shifted = shifted;
         HIPCHK(lat, Lc.gather(a, gmode, lat->stream));
         for (int k = 0; k < per_cell; ++k)
             HIPCHK(lat, hipMemcpyAsync(host + k * N + c0, d + k * cnt, cnt * sizeof(double), hipMemcpyDeviceToHost,
@@ -602,7 +638,7 @@ extern "C" lbm_status lbm_read_fields(lbm_lattice *lat, double *rho_host, double
         return set_err(LBM_ENOMEM, "host allocation failed");
     }
     dst = tmp.data();
-    lbm_status st = gather_range(lat, G_FIELDS, dst, 4);
+    lbm_status st = gather_range(lat, G_FIELDS, dst, 4, 0);
     if (st != LBM_OK) return st;
     if (rho_host) std::memcpy(rho_host, dst, (size_t)N * sizeof(double));
     if (u_host) std::memcpy(u_host, dst + N, (size_t)N * 3 * sizeof(double));
@@ -612,7 +648,13 @@ extern "C" lbm_status lbm_read_fields(lbm_lattice *lat, double *rho_host, double
 extern "C" lbm_status lbm_read_populations(lbm_lattice *lat, double *f_host) {
     CHECK_HANDLE(lat);
     if (!f_host) return set_err(LBM_EINVAL, "null output");
-    return gather_range(lat, G_POPS, f_host, lat->cfg.q);
+    return gather_range(lat, G_POPS, f_host, lat->cfg.q, 0);
+}
+
+extern "C" lbm_status lbm_read_state(lbm_lattice *lat, double *h_host) {
+    CHECK_HANDLE(lat);
+    if (!h_host) return set_err(LBM_EINVAL, "null output");
+    return gather_range(lat, G_POPS, h_host, lat->cfg.q, 1);
 }
 
 extern "C" lbm_status lbm_read_cells(lbm_lattice *lat, const int64_t *cells_host, int64_t n, double *f_host) {
@@ -638,8 +680,19 @@ extern "C" lbm_status lbm_read_cells(lbm_lattice *lat, const int64_t *cells_host
     return LBM_OK;
 }
 
+static lbm_status scatter_range(lbm_lattice *lat, const double *f_host, int64_t t, int shifted);
+
 extern "C" lbm_status lbm_write_populations(lbm_lattice *lat, const double *f_host, int64_t t) {
     CHECK_HANDLE(lat);
+    return scatter_range(lat, f_host, t, 0);
+}
+
+extern "C" lbm_status lbm_write_state(lbm_lattice *lat, const double *h_host, int64_t t) {
+    CHECK_HANDLE(lat);
+    return scatter_range(lat, h_host, t, 1);
+}
+
+static lbm_status scatter_range(lbm_lattice *lat, const double *f_host, int64_t t, int shifted) {
     if (!f_host) return set_err(LBM_EINVAL, "null input");
     if (t < 0) return set_err(LBM_EINVAL, "time must be >= 0");
     const int q = lat->cfg.q;
@@ -658,6 +711,7 @@ extern "C" lbm_status lbm_write_populations(lbm_lattice *lat, const double *f_ho
         a.cell0 = c0;
         a.count = cnt;
         a.in_f = d;
+        a.shifted = shifted;
         HIPCHK(lat, Lc.scatter(a, lat->stream));
         HIPCHK(lat, hipStreamSynchronize(lat->stream));
     }

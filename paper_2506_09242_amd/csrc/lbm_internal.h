@@ -58,8 +58,9 @@ struct StepParams {
     void *pops;               // population array, Q slots of `stride` elements
     const uint8_t *tags;      // device tags (TAGGED variants)
     const double *wall_u;     // [16][3] moving-wall velocities (device)
-    double *partials;         // [n_tiles][NRED] per-tile reduction partials
+    double *partials;         // [NRED][partial_stride] per-tile reduction partials
     long long stride;         // elements per population slot (padded plane)
+    long long partial_stride; // tiles per reduction slot in `partials`
     int nx, ny, nz;
     int tiles_x, tiles_y;     // tile grid in x and y (z: one plane per tile row)
     int n_tiles;              // tiles_x * tiles_y * nz
@@ -85,6 +86,7 @@ struct AuxParams {
     long long stride;
     int nx, ny, nz;
     int parity;               // layout parity of the state (0: natural)
+    int shifted;              // gathers/scatters of h_i = f_i - w_i rho0 (not f_i)
     double rho0;
     double force[3];
     long long cell0;          // first node of the chunk (range modes)
@@ -107,6 +109,10 @@ hipError_t launch_gather(const AuxParams &a, int gmode, hipStream_t s);
 template <int Q, int P>
 hipError_t launch_scatter(const AuxParams &a, hipStream_t s);
 
-hipError_t launch_finalize(const double *partials, int n_tiles, double *out, hipStream_t s);
+// Deterministic two-stage sum of the per-tile partials into out[NRED];
+// stage1 holds NRED * kFinalizeBlocks doubles.
+constexpr int kFinalizeBlocks = 256;
+hipError_t launch_finalize(const double *partials, long long partial_stride, int n_tiles, double *stage1, double *out,
+                           hipStream_t s);
 
 }  // namespace lbmd

@@ -322,7 +322,7 @@ __global__ __launch_bounds__(256) void k_collide_stream(StepParams p) {
         __syncthreads();
         if (threadIdx.x < NRED) {
             const int k = threadIdx.x;
-            p.partials[(long long)L * NRED + k] = (s_red[0][k] + s_red[1][k]) + (s_red[2][k] + s_red[3][k]);
+            p.partials[(long long)k * p.partial_stride + L] = (s_red[0][k] + s_red[1][k]) + (s_red[2][k] + s_red[3][k]);
         }
     }
 }
@@ -369,7 +369,7 @@ __device__ __forceinline__ void load_natural(const AuxParams &a, long long n, do
             const long long src = ((long long)sz * ny + sy) * nx + sx;
             if (is_fluid_tag(a.tags[src])) off = (long long)Vi::opp * a.stride + src;
         }
-        fo[i] = (double)f[off] + Vi::w * a.rho0;
+        fo[i] = a.shifted ? (double)f[off] : (double)f[off] + Vi::w * a.rho0;
     });
 }
 
@@ -379,6 +379,7 @@ __global__ __launch_bounds__(256) void k_gather(AuxParams a, int gmode) {
     if (t >= a.count) return;
     const long long n = gmode == G_CELLS ? a.cells[t] : a.cell0 + t;
     const bool fl = is_fluid_tag(a.tags[n]);
+    if (gmode == G_FIELDS) a.shifted = 0;
     double fo[Q];
     if (fl) {
         load_natural<Q, P>(a, n, fo);
@@ -419,7 +420,8 @@ __global__ __launch_bounds__(256) void k_scatter(AuxParams a) {
     sfor<Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         using Vi = V<Q, i>;
-        f[(long long)i * a.stride + n] = (S)(a.in_f[(long long)i * a.count + t] - Vi::w * a.rho0);
+        const double v = a.in_f[(long long)i * a.count + t];
+        f[(long long)i * a.stride + n] = (S)(a.shifted ? v : v - Vi::w * a.rho0);
     });
 }
 

@@ -65,6 +65,8 @@ SIGNATURES = {
     "lbm_read_populations": (C.c_int, [_P, _P]),
     "lbm_read_cells": (C.c_int, [_P, _P, C.c_int64, _P]),
     "lbm_write_populations": (C.c_int, [_P, _P, C.c_int64]),
+    "lbm_read_state": (C.c_int, [_P, _P]),
+    "lbm_write_state": (C.c_int, [_P, _P, C.c_int64]),
     "lbm_set_mlp": (C.c_int, [_P, _P, C.c_size_t]),
     "lbm_mlp_infer": (C.c_int, [_P, C.c_double, _P, C.c_int64, _P, _P]),
     "lbm_filter_snapshot": (C.c_int, [_P, C.c_int, _P, _P]),
@@ -283,6 +285,15 @@ class Lattice:
     def write_populations(self, f, t=0):
         a = np.ascontiguousarray(f, dtype=np.float64).reshape(self.q * self.N)
         _check(lib().lbm_write_populations(self.h, _ptr(a), int(t)))
+
+    def read_state(self):
+        h = np.empty((self.q,) + self.shape)
+        _check(lib().lbm_read_state(self.h, _ptr(h)))
+        return h
+
+    def write_state(self, h, t=0):
+        a = np.ascontiguousarray(h, dtype=np.float64).reshape(self.q * self.N)
+        _check(lib().lbm_write_state(self.h, _ptr(a), int(t)))
 
     def set_mlp(self, params):
         p = np.ascontiguousarray(params, dtype=np.float32)

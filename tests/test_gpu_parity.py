@@ -201,22 +201,36 @@ def test_fused_and_standalone_reductions_agree():
 
 
 # --------------------------------------------------------- checkpoint (T11)
-@pytest.mark.parametrize("prec", [lbm.LBM_F64, lbm.LBM_F32])
-def test_checkpoint_roundtrip_bitwise(prec):
+@pytest.mark.parametrize("prec", [lbm.LBM_F64, lbm.LBM_F32, lbm.LBM_F16S])
+@pytest.mark.parametrize("steps", [10, 11])
+def test_checkpoint_roundtrip_bitwise(prec, steps):
+    """Shifted-state checkpoints restore bit for bit in every precision and
+    parity; unshifted ones are exact for FP32/FP16 storage and within one FP64
+    rounding of f for FP64 storage."""
     nx, ny, nz = 33, 17, 12
     tags = inputs.random_tags(nx, ny, nz, seed=31, solid_frac=0.2, wall_frac=0.05)
     rho, u = inputs.random_fields(nx, ny, nz, seed=32)
     kw = dict(q=19, prec=prec, tau=0.7, wall_velocity=[(0.04, 0, 0), (0, 0, 0.03)])
     A = lbm.Lattice(tags, **kw)
     A.init_equilibrium(rho, u)
-    A.step(11)  # odd parity
-    ck = A.read_populations()
+    A.step(steps)
+    ck = A.read_state()
+    fk = A.read_populations()
     B = lbm.Lattice(tags, **kw)
-    B.write_populations(ck, t=A.time)
-    assert B.time == 11
+    B.write_state(ck, t=A.time)
+    assert B.time == steps
+    C = lbm.Lattice(tags, **kw)
+    C.write_populations(fk, t=A.time)
     A.step(8)
     B.step(8)
-    assert np.array_equal(A.read_populations(), B.read_populations())
+    C.step(8)
+    fa = A.read_populations()
+    assert np.array_equal(fa, B.read_populations())
+    fc = C.read_populations()
+    if prec == lbm.LBM_F64:
+        assert max_rel_pop_error(fc, fa, tags) <= 1e-14
+    else:
+        assert np.array_equal(fa, fc)
 
 
 def test_read_cells_matches_full_read():
