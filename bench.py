@@ -32,6 +32,7 @@ WORKLOADS = {
     "tgv512_d3q27_smag": "D3Q27 BGK+Smagorinsky(Cs=0.1) Taylor-Green 512^3, u0=0.05, Re=1600",
     "porous400_d3q19_trt": "D3Q19 TRT(3/16) body-force porous 400^3, phi=0.20, corr. length 8",
     "tgv32_d3q19_bgk": "D3Q19 BGK Taylor-Green 32^3, u0=0.04, Re=100 (cache-resident)",
+    "closure_tgv128_d3q27": "learned closure: D3Q27 TGV Re=1600, fine 512^3 -> coarse 128^3, MLP vs Smagorinsky vs BGK",
 }
 
 
@@ -144,6 +145,9 @@ def main():
     ap.add_argument("--dtypes", default="f32,f64,f16s", help="first one is the reported value")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=20)
+    ap.add_argument("--closure-fine", type=int, default=512)
+    ap.add_argument("--closure-samples", type=int, default=1_000_000)
+    ap.add_argument("--closure-epochs", type=int, default=30)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -175,6 +179,20 @@ def main():
         return
 
     from paper_2506_09242_amd import lbm
+    if args.workload == "closure_tgv128_d3q27":
+        from paper_2506_09242_amd import closure
+        log = lambda m: print("# " + m, file=sys.stderr, flush=True)
+        res, _ = closure.experiment(n_fine=args.closure_fine, factor=4, n_snap=16,
+                                    n_samples=args.closure_samples, epochs=args.closure_epochs, log=log)
+        mlp = res["coarse"]["mlp"]
+        print(json.dumps({"metric": METRIC, "value": round(mlp["MLUPS"], 2), "unit": "MLUPS", "n_gpus": 1,
+                          "steps": None, "warmup": 0, "higher_is_better": True, "scaling": "weak",
+                          "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+                          "config": {"workload": args.workload, "n_fine": args.closure_fine,
+                                     "n_coarse": args.closure_fine // 4, "samples": args.closure_samples,
+                                     "epochs": args.closure_epochs},
+                          "closure": res}), flush=True)
+        return
     tags, kw, rho, u, wl_cfg = build_workload(args.workload)
     prec_names = [p.strip() for p in args.dtypes.split(",") if p.strip()]
     results = {}

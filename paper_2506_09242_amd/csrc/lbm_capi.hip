@@ -45,6 +45,7 @@ struct lbm_lattice {
     double *d_partials = nullptr;   // [NRED][max_tiles]
     long long max_tiles = 0;
     double *d_stage1 = nullptr;     // [NRED][kFinalizeBlocks]
+    uint8_t *d_tile_tag = nullptr;  // [max_tiles] tile classification of the current tiling
     double *d_series = nullptr;     // [series_cap][NRED]
     long long series_cap = 0;
     void *d_mlp = nullptr;          // packed closure block (lbm_mlp.hip)
@@ -55,7 +56,8 @@ struct lbm_lattice {
     int ms = MS_BGK;                // compiled model set
     bool tagged = true;
     int uniform_tag = LBM_TAG_BGK;
-    int tx_log2 = 8;
+    int tx_log2 = 8;                // log2(threads per tile row)
+    int vn = 1;                     // nodes per thread
     int tiles_x = 1, tiles_y = 1, n_tiles = 1;
     long long n_fluid = 0;
     bool failed = false;
@@ -138,20 +140,25 @@ lbm_status validate(const lbm_config *c) {
     return LBM_OK;
 }
 
-void choose_tiles(lbm_lattice *L, int txl) {
+void choose_tiles(lbm_lattice *L, int txl, int vn) {
     L->tx_log2 = txl;
-    const int TX = 1 << txl, TY = 256 >> txl;
+    L->vn = vn;
+    const int TX = (1 << txl) * vn, TY = 256 >> txl;
     L->tiles_x = (L->cfg.nx + TX - 1) / TX;
     L->tiles_y = (L->cfg.ny + TY - 1) / TY;
     L->n_tiles = L->tiles_x * L->tiles_y * L->cfg.nz;
 }
 
-// Default tile width: the smallest padded row (ceil(nx/tx)*tx), larger tx on ties.
-int default_txl(int nx) {
+// Nodes per thread by storage precision (wider accesses for narrow types).
+int default_vn(int prec) { return prec == LBM_F64 ? 1 : 2; }
+
+// Default threads per tile row: the smallest padded row (ceil(nx/TX)*TX with
+// TX = vn << txl), larger tiles on ties.
+int default_txl(int nx, int vn) {
     int best = 8;
-    long long best_pad = (long long)((nx + 255) / 256) * 256;
+    long long best_pad = (long long)((nx + 256 * vn - 1) / (256 * vn)) * 256 * vn;
     for (int l = 7; l >= 5; --l) {
-        const int tx = 1 << l;
+        const int tx = (1 << l) * vn;
         const long long pad = (long long)((nx + tx - 1) / tx) * tx;
         if (pad < best_pad) {
             best_pad = pad;
@@ -166,6 +173,7 @@ StepParams step_params(const lbm_lattice *L) {
     const lbm_config &c = L->cfg;
     p.pops = L->d_pops;
     p.tags = L->d_tags;
+    p.tile_tag = L->d_tile_tag;
     p.wall_u = L->d_wall;
     p.partials = L->d_partials;
     p.partial_stride = L->max_tiles;
@@ -178,6 +186,7 @@ StepParams step_params(const lbm_lattice *L) {
     p.n_tiles = L->n_tiles;
     p.tiles_per_xcd = (L->n_tiles + 7) / 8;
     p.tx_log2 = L->tx_log2;
+    p.vn = L->vn;
     p.uniform_tag = L->uniform_tag;
     p.has_force = (c.force[0] != 0.0 || c.force[1] != 0.0 || c.force[2] != 0.0) ? 1 : 0;
     p.has_mlp = L->has_mlp ? 1 : 0;
@@ -266,6 +275,40 @@ __global__ __launch_bounds__(256) void k_finalize2(const double *stage1, int nb,
     }
 }
 
+// One block per tile: load the tile's tags with a one-node halo (periodic)
+// and report the tag if every one of them is the same fluid tag, else 0.
+__global__ __launch_bounds__(256) void k_tile_classify(StepParams p, uint8_t *out) {
+    __shared__ int s_first, s_same;
+    const int L = blockIdx.x;
+    const int txl = p.tx_log2;
+    const int TX = (1 << txl) * p.vn, TY = 256 >> txl;
+    const int tix = L % p.tiles_x, rem = L / p.tiles_x;
+    const int tiy = rem % p.tiles_y, z = rem / p.tiles_y;
+    const int x0 = tix * TX, y0 = tiy * TY;
+    const int WX = TX + 2, WY = TY + 2;
+    if (threadIdx.x == 0) {
+        s_first = p.tags[((long long)z * p.ny + y0) * p.nx + x0];
+        s_same = 1;
+    }
+    __syncthreads();
+    const int first = s_first;
+    bool same = is_fluid_tag(first);
+    for (int k = threadIdx.x; k < WX * WY * 3; k += 256) {
+        const int ax = k % WX, r = k / WX, ay = r % WY, az = r / WY;
+        const int gx = (x0 + ax - 1 + p.nx) % p.nx, gy = (y0 + ay - 1 + p.ny) % p.ny;
+        const int gz = (z + az - 1 + p.nz) % p.nz;
+        if (p.tags[((long long)gz * p.ny + gy) * p.nx + gx] != first) same = false;
+    }
+    if (!same) s_same = 0;
+    __syncthreads();
+    if (threadIdx.x == 0) out[L] = s_same ? (uint8_t)first : (uint8_t)0;
+}
+
+hipError_t launch_tile_classify(const StepParams &p, uint8_t *out, hipStream_t s) {
+    k_tile_classify<<<p.n_tiles, 256, 0, s>>>(p, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_finalize(const double *partials, long long partial_stride, int n_tiles, double *stage1, double *out,
                            hipStream_t s) {
     const int nb = std::min(kFinalizeBlocks, std::max(1, (n_tiles + 255) / 256));
@@ -339,7 +382,10 @@ static lbm_status create_impl(const lbm_config *cfg, const uint8_t *tags_host, v
     L->ms = ms;
     L->tagged = tagged;
     L->uniform_tag = only;
-    choose_tiles(L, default_txl(cfg->nx));
+    {
+        const int vn = default_vn(cfg->prec);
+        choose_tiles(L, default_txl(cfg->nx, vn), vn);
+    }
     static const char *msname[] = {"bgk", "trt", "bgk+smag", "bgk+smag+mlp", "all"};
     int msi = 0;
     for (int k = 0; k < kNumModelSets; ++k)
@@ -380,10 +426,11 @@ static lbm_status create_impl(const lbm_config *cfg, const uint8_t *tags_host, v
     }
     // Partials sized for the tiling with the most tiles over every allowed tile width.
     long long max_tiles = 0;
-    for (int l = 5; l <= 8; ++l) {
-        const long long tx = 1LL << l, ty = 256 >> l;
-        max_tiles = std::max(max_tiles, ((cfg->nx + tx - 1) / tx) * ((cfg->ny + ty - 1) / ty) * cfg->nz);
-    }
+    for (int vn = 1; vn <= 2; ++vn)
+        for (int l = 5; l <= 8; ++l) {
+            const long long tx = (1LL << l) * vn, ty = 256 >> l;
+            max_tiles = std::max(max_tiles, ((cfg->nx + tx - 1) / tx) * ((cfg->ny + ty - 1) / ty) * cfg->nz);
+        }
     L->max_tiles = max_tiles;
     e = hipMalloc(&L->d_partials, (size_t)max_tiles * NRED * sizeof(double));
     if (e != hipSuccess) {
@@ -397,9 +444,16 @@ static lbm_status create_impl(const lbm_config *cfg, const uint8_t *tags_host, v
         L->d_stage1 = nullptr;
         return bail(set_err(LBM_ENOMEM, "hipMalloc of reduction stage buffer failed"));
     }
+    e = hipMalloc(&L->d_tile_tag, (size_t)max_tiles);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        L->d_tile_tag = nullptr;
+        return bail(set_err(LBM_ENOMEM, "hipMalloc of tile classes failed"));
+    }
     e = hipMemcpyAsync(L->d_tags, tags_host, (size_t)N, hipMemcpyHostToDevice, L->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(L->d_wall, cfg->wall_velocity, 16 * 3 * sizeof(double), hipMemcpyHostToDevice, L->stream);
+    if (e == hipSuccess && L->tagged) e = launch_tile_classify(step_params(L), L->d_tile_tag, L->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
     if (e != hipSuccess) return bail(lbmd_fail_hip(nullptr, e, "tag upload"));
     *out = L;
@@ -427,6 +481,7 @@ extern "C" void lbm_destroy(lbm_lattice *lat) {
     if (lat->d_wall) (void)hipFree(lat->d_wall);
     if (lat->d_partials) (void)hipFree(lat->d_partials);
     if (lat->d_stage1) (void)hipFree(lat->d_stage1);
+    if (lat->d_tile_tag) (void)hipFree(lat->d_tile_tag);
     if (lat->d_series) (void)hipFree(lat->d_series);
     lbmd_free_mlp(lat);
     delete lat;
@@ -434,11 +489,16 @@ extern "C" void lbm_destroy(lbm_lattice *lat) {
 
 extern "C" lbm_status lbm_set_launch(lbm_lattice *lat, int tx, int ty) {
     CHECK_HANDLE(lat);
+    const int vn = (tx > 0 && ty > 0) ? tx * ty / 256 : 0;
     int l = -1;
-    for (int k = 5; k <= 8; ++k)
-        if (tx == (1 << k)) l = k;
-    if (l < 0 || tx * ty != 256) return set_err(LBM_EINVAL, "tile must be tx in {32,64,128,256} with tx*ty = 256");
-    choose_tiles(lat, l);
+    if ((vn == 1 || vn == 2) && tx * ty == 256 * vn)
+        for (int k = 5; k <= 8; ++k)
+            if (tx == (1 << k) * vn) l = k;
+    if (l < 0)
+        return set_err(LBM_EINVAL, "tile must have tx*ty = 256 (one node per thread) or 512 (two), "
+                                   "tx / (tx*ty/256) in {32, 64, 128, 256}");
+    choose_tiles(lat, l, vn);
+    if (lat->tagged) HIPCHK(lat, launch_tile_classify(step_params(lat), lat->d_tile_tag, lat->stream));
     return LBM_OK;
 }
 

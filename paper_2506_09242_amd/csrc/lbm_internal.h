@@ -57,6 +57,8 @@ struct MlpDev {
 struct StepParams {
     void *pops;               // population array, Q slots of `stride` elements
     const uint8_t *tags;      // device tags (TAGGED variants)
+    const uint8_t *tile_tag;  // per tile: the single fluid tag of the tile and its
+                              // one-node halo, or 0 if the tile needs its tag tile
     const double *wall_u;     // [16][3] moving-wall velocities (device)
     double *partials;         // [NRED][partial_stride] per-tile reduction partials
     long long stride;         // elements per population slot (padded plane)
@@ -65,7 +67,8 @@ struct StepParams {
     int tiles_x, tiles_y;     // tile grid in x and y (z: one plane per tile row)
     int n_tiles;              // tiles_x * tiles_y * nz
     int tiles_per_xcd;        // ceil(n_tiles / 8)
-    int tx_log2;              // tile width = 1 << tx_log2, height = 256 >> tx_log2
+    int tx_log2;              // log2(threads per tile row); tile height = 256 >> tx_log2
+    int vn;                   // consecutive nodes per thread (1 or 2); tile width = vn << tx_log2
     int uniform_tag;          // model tag of every node (untagged variants)
     int has_force;
     int has_mlp;              // closure parameters uploaded
@@ -112,6 +115,9 @@ hipError_t launch_scatter(const AuxParams &a, hipStream_t s);
 // Deterministic two-stage sum of the per-tile partials into out[NRED];
 // stage1 holds NRED * kFinalizeBlocks doubles.
 constexpr int kFinalizeBlocks = 256;
+// Classify every tile of the current tiling (see StepParams::tile_tag).
+hipError_t launch_tile_classify(const StepParams &p, uint8_t *out, hipStream_t s);
+
 hipError_t launch_finalize(const double *partials, long long partial_stride, int n_tiles, double *stage1, double *out,
                            hipStream_t s);
 

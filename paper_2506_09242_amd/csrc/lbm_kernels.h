@@ -40,16 +40,168 @@
 
 namespace lbmd {
 
-// Largest tag tile staged in LDS: (tx+2)*(ty+2)*3 over tx in {32..256}.
-constexpr int kTileBytes = 2336;
+// Largest tag tile staged in LDS: (TX+2)*(TY+2)*3 bytes, TX = cells per tile
+// row (threads per row x nodes per thread), TY = rows; worst case TX = 512, TY = 1.
+constexpr int kTileBytes = 4640;
 
 __device__ __forceinline__ int wrap_idx(int v, int n) { return v < 0 ? v + n : (v >= n ? v % n : v); }
 
-template <int Q, int P, int MS, bool TAGGED, int MODE, int PARITY>
+// V consecutive elements of one slot (a single, possibly unaligned, vector access).
+template <int V, typename S>
+__device__ __forceinline__ void vload(S (&d)[V], const S *p) {
+    __builtin_memcpy(d, p, sizeof(S) * V);
+}
+template <int V, typename S>
+__device__ __forceinline__ void vstore(S *p, const S (&d)[V]) {
+    __builtin_memcpy(p, d, sizeof(S) * V);
+}
+
+// FP64 reduction terms of one node's loaded (time-t) populations, added to red.
+template <int Q, typename C>
+__device__ __forceinline__ void node_reduce(const C (&h)[Q], bool live, const StepParams &p, double (&red)[NRED]) {
+    double dr = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+    sfor<Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        using Vi = V<Q, i>;
+        const double v = (double)h[i];
+        dr += v;
+        if constexpr (Vi::x != 0) jx += Vi::x * v;
+        if constexpr (Vi::y != 0) jy += Vi::y * v;
+        if constexpr (Vi::z != 0) jz += Vi::z * v;
+    });
+    const double rho = p.rho0 + dr;
+    const double px = jx + 0.5 * p.force[0], py = jy + 0.5 * p.force[1], pz = jz + 0.5 * p.force[2];
+    const double ux = px / rho, uy = py / rho, uz = pz / rho;
+    const double uu = ux * ux + uy * uy + uz * uz;
+    const bool ok = isfinite(rho) && isfinite(uu);
+    const bool use = live && ok;
+    red[0] += use ? dr : 0.0;
+    red[1] += use ? px : 0.0;
+    red[2] += use ? py : 0.0;
+    red[3] += use ? pz : 0.0;
+    red[4] += use ? ux : 0.0;
+    red[5] += use ? uy : 0.0;
+    red[6] += use ? uz : 0.0;
+    red[7] += use ? 0.5 * uu : 0.0;
+    red[8] += use ? 0.5 * rho * uu : 0.0;
+    red[9] += (live && !ok) ? 1.0 : 0.0;
+}
+
+// Collision of one node in shifted form (pair split, Guo forcing).  Every lane
+// of the wave must call it (the learned closure is evaluated wave-wide).
+template <int Q, typename C, int MS>
+__device__ __forceinline__ void collide_node(const C (&h)[Q], int tag, bool live, const StepParams &p, C (&hs)[Q]) {
+    constexpr int H = (Q - 1) / 2;
+    C drho = C(0), jx = C(0), jy = C(0), jz = C(0);
+    sfor<Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        using Vi = V<Q, i>;
+        drho += h[i];
+        if constexpr (Vi::x == 1) jx += h[i];
+        if constexpr (Vi::x == -1) jx -= h[i];
+        if constexpr (Vi::y == 1) jy += h[i];
+        if constexpr (Vi::y == -1) jy -= h[i];
+        if constexpr (Vi::z == 1) jz += h[i];
+        if constexpr (Vi::z == -1) jz -= h[i];
+    });
+    const C Fx = (C)p.force[0], Fy = (C)p.force[1], Fz = (C)p.force[2];
+    const C rho = (C)p.rho0 + drho;
+    const C inv_rho = C(1) / rho;
+    const C ux = (jx + C(0.5) * Fx) * inv_rho;
+    const C uy = (jy + C(0.5) * Fy) * inv_rho;
+    const C uz = (jz + C(0.5) * Fz) * inv_rho;
+    const C uu = ux * ux + uy * uy + uz * uz;
+    const C uF = ux * Fx + uy * Fy + uz * Fz;
+
+    // equilibrium, even/odd parts per pair k = 1..H (direction k, opposite k+H)
+    C ev[H + 1], od[H + 1], cuk[H + 1];
+    ev[0] = C(V<Q, 0>::w) * (drho - C(1.5) * rho * uu);
+    od[0] = C(0);
+    cuk[0] = C(0);
+    sfor<H>([&](auto K) {
+        constexpr int k = decltype(K)::value + 1;
+        using Vk = V<Q, k>;
+        C cu = C(0);
+        if constexpr (Vk::x != 0) cu += C(Vk::x) * ux;
+        if constexpr (Vk::y != 0) cu += C(Vk::y) * uy;
+        if constexpr (Vk::z != 0) cu += C(Vk::z) * uz;
+        cuk[k] = cu;
+        ev[k] = C(Vk::w) * (drho + rho * (C(4.5) * cu * cu - C(1.5) * uu));
+        od[k] = C(Vk::w) * C(3) * rho * cu;
+    });
+
+    // relaxation rates from the node's model
+    C wp = (C)p.omega, wm = (C)p.omega;
+    if constexpr ((MS & MS_TRT) != 0) {
+        if (tag == LBM_TAG_TRT) wm = (C)p.omega_minus;
+    }
+    if constexpr ((MS & (MS_SMAG | MS_MLP)) != 0) {
+        // Pi_ab = sum c_a c_b (h - heq): only even parts contribute.
+        C pxx = C(0), pyy = C(0), pzz = C(0), pxy = C(0), pxz = C(0), pyz = C(0);
+        sfor<H>([&](auto K) {
+            constexpr int k = decltype(K)::value + 1;
+            using Vk = V<Q, k>;
+            const C ne = (h[k] + h[k + H]) - C(2) * ev[k];
+            if constexpr (Vk::x != 0) pxx += ne;
+            if constexpr (Vk::y != 0) pyy += ne;
+            if constexpr (Vk::z != 0) pzz += ne;
+            if constexpr (Vk::x * Vk::y != 0) pxy += C(Vk::x * Vk::y) * ne;
+            if constexpr (Vk::x * Vk::z != 0) pxz += C(Vk::x * Vk::z) * ne;
+            if constexpr (Vk::y * Vk::z != 0) pyz += C(Vk::y * Vk::z) * ne;
+        });
+        const C qn = sqrt(pxx * pxx + pyy * pyy + pzz * pzz + C(2) * (pxy * pxy + pxz * pxz + pyz * pyz));
+        const C tau0 = (C)p.tau;
+        const C tau_s = C(0.5) * (tau0 + sqrt(tau0 * tau0 + (C)p.smag_c * qn * inv_rho));
+        C tau_eff = tau_s;
+        if constexpr ((MS & MS_MLP) != 0) {
+            const bool want = live && tag == LBM_TAG_BGK_MLP;
+            if (p.has_mlp && __any(want)) {
+                const float feat[7] = {(float)pxx, (float)pyy, (float)pzz, (float)pxy,
+                                       (float)pxz, (float)pyz, (float)rho};
+                const float sp = mlp_wave_eval(p.mlp, feat);
+                const C nu0 = (C)p.nu0;
+                const C nut = nu0 * (C)sp;
+                if (isfinite(nut) && nut <= C(10) * nu0) {
+                    if (tag == LBM_TAG_BGK_MLP) tau_eff = C(3) * (nu0 + nut) + C(0.5);
+                }
+            }
+        }
+        if (tag == LBM_TAG_BGK_SMAG || tag == LBM_TAG_BGK_MLP) {
+            wp = C(1) / tau_eff;
+            wm = wp;
+        }
+    }
+
+    const C gp = C(1) - C(0.5) * wp, gm = C(1) - C(0.5) * wm;
+    const C F0 = C(V<Q, 0>::w) * C(-3) * uF;
+    hs[0] = h[0] - wp * (h[0] - ev[0]) + gp * F0;
+    sfor<H>([&](auto K) {
+        constexpr int k = decltype(K)::value + 1;
+        using Vk = V<Q, k>;
+        C cF = C(0);
+        if constexpr (Vk::x != 0) cF += C(Vk::x) * Fx;
+        if constexpr (Vk::y != 0) cF += C(Vk::y) * Fy;
+        if constexpr (Vk::z != 0) cF += C(Vk::z) * Fz;
+        const C Fe = C(Vk::w) * (C(9) * cuk[k] * cF - C(3) * uF);
+        const C Fo = C(Vk::w) * C(3) * cF;
+        const C hp = C(0.5) * (h[k] + h[k + H]);
+        const C hm = C(0.5) * (h[k] - h[k + H]);
+        const C A = gp * Fe - wp * (hp - ev[k]);
+        const C B = gm * Fo - wm * (hm - od[k]);
+        hs[k] = h[k] + A + B;
+        hs[k + H] = h[k + H] + A - B;
+    });
+}
+
+// The fused collide-and-stream step.  Each thread updates VN consecutive
+// nodes of one row; a tile is (threads per row * VN) x (256 / threads per
+// row) nodes of one z-plane.  Accesses of the VN nodes to one slot are a
+// single vector load/store unless a wall, a periodic wrap or a ragged row
+// end splits them.
+template <int Q, int P, int MS, bool TAGGED, int MODE, int PARITY, int VN>
 __global__ __launch_bounds__(256) void k_collide_stream(StepParams p) {
     using S = typename Prec<P>::S;
     using C = typename Prec<P>::C;
-    constexpr int H = (Q - 1) / 2;
 
     // XCD-aware tile order: hardware deals workgroups round-robin over the 8
     // XCDs, so workgroup w runs on XCD w % 8; give each XCD a contiguous run
@@ -58,254 +210,209 @@ __global__ __launch_bounds__(256) void k_collide_stream(StepParams p) {
     const int L = (wg & 7) * p.tiles_per_xcd + (wg >> 3);
     if (L >= p.n_tiles) return;  // uniform for the block
 
-    const int txl = p.tx_log2;
-    const int TX = 1 << txl, TY = 256 >> txl;
+    const int txl = p.tx_log2;            // log2(threads per tile row)
+    const int TXT = 1 << txl, TY = 256 >> txl;
+    const int TX = TXT * VN;              // nodes per tile row
     const int tix = L % p.tiles_x;
     const int rem = L / p.tiles_x;
     const int tiy = rem % p.tiles_y;
     const int z = rem / p.tiles_y;
-    const int lx = threadIdx.x & (TX - 1), ly = threadIdx.x >> txl;
-    const int x0 = tix << txl, y0 = tiy * TY;
-    const int x = x0 + lx, y = y0 + ly;
+    const int lx = threadIdx.x & (TXT - 1), ly = threadIdx.x >> txl;
+    const int x0 = tix * TX, y0 = tiy * TY;
+    const int xb = x0 + VN * lx, y = y0 + ly;
     const int nx = p.nx, ny = p.ny, nz = p.nz;
-    const bool active = (x < nx) && (y < ny);
+    const bool row_ok = y < ny;
 
-    int tag = p.uniform_tag;
-    uint32_t wall = 0;  // bit i: node x + c_i is not fluid
+    int tag[VN];
+    uint32_t wall[VN];  // bit i: node x + c_i is not fluid
+    bool act[VN];
+#pragma unroll
+    for (int e = 0; e < VN; ++e) {
+        tag[e] = p.uniform_tag;
+        wall[e] = 0;
+        act[e] = row_ok && (xb + e < nx);
+    }
     __shared__ uint8_t s_tag[TAGGED ? kTileBytes : 1];
     const int WX = TX + 2, WY = TY + 2;
-    const int cidx = (WY + ly + 1) * WX + lx + 1;
+    const int cidx = (WY + ly + 1) * WX + VN * lx + 1;  // centre of node 0 in the tag tile
     if constexpr (TAGGED) {
-        const int total = WX * WY * 3;
-        for (int k = threadIdx.x; k < total; k += 256) {
-            const int ax = k % WX;
-            const int r = k / WX;
-            const int ay = r % WY;
-            const int az = r / WY;
-            const int gx = wrap_idx(x0 + ax - 1, nx);
-            const int gy = wrap_idx(y0 + ay - 1, ny);
-            const int gz = wrap_idx(z + az - 1, nz);
-            s_tag[k] = p.tags[((long long)gz * ny + gy) * nx + gx];
-        }
-        __syncthreads();
-        tag = s_tag[cidx];
-        sfor<Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            if constexpr (i > 0) {
-                using Vi = V<Q, i>;
-                const int t = s_tag[cidx + (Vi::z * WY + Vi::y) * WX + Vi::x];
-                if (!is_fluid_tag(t)) wall |= 1u << i;
+        // Tiles whose one-node halo holds a single fluid model (the interior of a
+        // walled domain) skip the tag tile; the branch is uniform per block.
+        const int tile_tag = p.tile_tag[L];
+        if (tile_tag != 0) {
+#pragma unroll
+            for (int e = 0; e < VN; ++e) tag[e] = tile_tag;
+        } else {
+            const int total = WX * WY * 3;
+            for (int k = threadIdx.x; k < total; k += 256) {
+                const int ax = k % WX;
+                const int r = k / WX;
+                const int ay = r % WY;
+                const int az = r / WY;
+                const int gx = wrap_idx(x0 + ax - 1, nx);
+                const int gy = wrap_idx(y0 + ay - 1, ny);
+                const int gz = wrap_idx(z + az - 1, nz);
+                s_tag[k] = p.tags[((long long)gz * ny + gy) * nx + gx];
             }
-        });
+            __syncthreads();
+#pragma unroll
+            for (int e = 0; e < VN; ++e) {
+                tag[e] = s_tag[cidx + e];
+                sfor<Q>([&](auto I) {
+                    constexpr int i = decltype(I)::value;
+                    if constexpr (i > 0) {
+                        using Vi = V<Q, i>;
+                        const int t = s_tag[cidx + e + (Vi::z * WY + Vi::y) * WX + Vi::x];
+                        if (!is_fluid_tag(t)) wall[e] |= 1u << i;
+                    }
+                });
+            }
+        }
     }
-    const bool live = active && (!TAGGED || is_fluid_tag(tag));
+    bool live[VN];
+    bool all_act = true, all_live = true;
+    uint32_t wall_any = 0;
+#pragma unroll
+    for (int e = 0; e < VN; ++e) {
+        live[e] = act[e] && (!TAGGED || is_fluid_tag(tag[e]));
+        all_act = all_act && act[e];
+        all_live = all_live && live[e];
+        wall_any |= wall[e];
+    }
 
-    // Neighbour offsets with periodic wrap; index 1 + c for c in {-1, 0, 1}.
-    const int xc = active ? x : 0, yc = active ? y : 0;
-    const int xo[3] = {xc == 0 ? nx - 1 : xc - 1, xc, xc + 1 == nx ? 0 : xc + 1};
-    const int yo[3] = {(yc == 0 ? ny - 1 : yc - 1) * nx, yc * nx, (yc + 1 == ny ? 0 : yc + 1) * nx};
+    // Row offsets (periodic) and x of each node with its +-1 neighbours.
+    const int yc = row_ok ? y : 0;
     const int nxy = nx * ny;
+    const int yo[3] = {(yc == 0 ? ny - 1 : yc - 1) * nx, yc * nx, (yc + 1 == ny ? 0 : yc + 1) * nx};
     const int zo[3] = {(z == 0 ? nz - 1 : z - 1) * nxy, z * nxy, (z + 1 == nz ? 0 : z + 1) * nxy};
-    const int n = zo[1] + yo[1] + xo[1];
+    int xn[VN][3];
+#pragma unroll
+    for (int e = 0; e < VN; ++e) {
+        const int xe = act[e] ? xb + e : 0;
+        xn[e][0] = xe == 0 ? nx - 1 : xe - 1;
+        xn[e][1] = xe;
+        xn[e][2] = xe + 1 == nx ? 0 : xe + 1;
+    }
+    const int row_own = zo[1] + yo[1];
     const long long st = p.stride;
     S *__restrict__ f = static_cast<S *>(p.pops);
 
-    // ---- pull the node's populations
-    C h[Q];
-    if (live) {
-        sfor<Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            using Vi = V<Q, i>;
-            long long off;
-            if constexpr (PARITY == 0 || i == 0) {
-                off = (long long)i * st + n;
+    // ---- pull the nodes' populations
+    C h[VN][Q];
+    sfor<Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        using Vi = V<Q, i>;
+        if constexpr (PARITY == 0 || i == 0) {
+            const S *src = f + (long long)i * st + row_own;
+            if (all_act) {
+                S tmp[VN];
+                vload<VN>(tmp, src + xb);
+#pragma unroll
+                for (int e = 0; e < VN; ++e) h[e][i] = (C)tmp[e];
             } else {
-                const int src = zo[1 - Vi::z] + yo[1 - Vi::y] + xo[1 - Vi::x];
-                const long long o_nb = (long long)Vi::opp * st + src;
-                if constexpr (TAGGED) {
-                    const bool wb = (wall >> Vi::opp) & 1u;
-                    off = wb ? (long long)i * st + n : o_nb;
-                } else {
-                    off = o_nb;
+#pragma unroll
+                for (int e = 0; e < VN; ++e) h[e][i] = act[e] ? (C)src[xn[e][1]] : C(0);
+            }
+        } else {
+            // direction i arrives from x - c_i (slot opp), or from the node's own
+            // slot i when x - c_i is a wall
+            const S *nb = f + (long long)Vi::opp * st + zo[1 - Vi::z] + yo[1 - Vi::y];
+            const S *own = f + (long long)i * st + row_own;
+            const int start = xb - Vi::x;
+            const bool wall_hit = TAGGED && ((wall_any >> Vi::opp) & 1u);
+            if (all_act && !wall_hit && start >= 0 && start + VN <= nx) {
+                S tmp[VN];
+                vload<VN>(tmp, nb + start);
+#pragma unroll
+                for (int e = 0; e < VN; ++e) h[e][i] = (C)tmp[e];
+            } else {
+#pragma unroll
+                for (int e = 0; e < VN; ++e) {
+                    const bool wb = TAGGED && ((wall[e] >> Vi::opp) & 1u);
+                    h[e][i] = act[e] ? (C)(wb ? own[xn[e][1]] : nb[xn[e][1 - Vi::x]]) : C(0);
                 }
             }
-            h[i] = (C)f[off];
-        });
-    } else {
-        sfor<Q>([&](auto I) { h[decltype(I)::value] = C(0); });
-    }
+        }
+    });
 
-    // ---- FP64 reductions of the loaded (time-t) state
     double red[NRED];
     if constexpr (MODE != MODE_STEP) {
-        double dr = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
-        sfor<Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            using Vi = V<Q, i>;
-            const double v = (double)h[i];
-            dr += v;
-            if constexpr (Vi::x != 0) jx += Vi::x * v;
-            if constexpr (Vi::y != 0) jy += Vi::y * v;
-            if constexpr (Vi::z != 0) jz += Vi::z * v;
-        });
-        const double rho = p.rho0 + dr;
-        const double px = jx + 0.5 * p.force[0], py = jy + 0.5 * p.force[1], pz = jz + 0.5 * p.force[2];
-        const double ux = px / rho, uy = py / rho, uz = pz / rho;
-        const double uu = ux * ux + uy * uy + uz * uz;
-        const bool ok = isfinite(rho) && isfinite(uu);
-        const bool use = live && ok;
-        red[0] = use ? dr : 0.0;
-        red[1] = use ? px : 0.0;
-        red[2] = use ? py : 0.0;
-        red[3] = use ? pz : 0.0;
-        red[4] = use ? ux : 0.0;
-        red[5] = use ? uy : 0.0;
-        red[6] = use ? uz : 0.0;
-        red[7] = use ? 0.5 * uu : 0.0;
-        red[8] = use ? 0.5 * rho * uu : 0.0;
-        red[9] = (live && !ok) ? 1.0 : 0.0;
+#pragma unroll
+        for (int k = 0; k < NRED; ++k) red[k] = 0.0;
+#pragma unroll
+        for (int e = 0; e < VN; ++e) node_reduce<Q, C>(h[e], live[e], p, red);
     }
 
     if constexpr (MODE != MODE_REDUCE) {
-        // ---- moments
-        C drho = C(0), jx = C(0), jy = C(0), jz = C(0);
+        C hs[VN][Q];
+#pragma unroll
+        for (int e = 0; e < VN; ++e) collide_node<Q, C, MS>(h[e], tag[e], live[e], p, hs[e]);
+
+        // moving-wall term where x + c_i is a wall (zero for resting walls)
+        if constexpr (TAGGED) {
+            if (wall_any) {
+#pragma unroll
+                for (int e = 0; e < VN; ++e) {
+                    sfor<Q>([&](auto I) {
+                        constexpr int i = decltype(I)::value;
+                        using Vi = V<Q, i>;
+                        if constexpr (i > 0) {
+                            if ((wall[e] >> i) & 1u) {
+                                const int t = s_tag[cidx + e + (Vi::z * WY + Vi::y) * WX + Vi::x];
+                                if (t >= LBM_TAG_WALL0) {
+                                    const double *uw = p.wall_u + 3 * (t - LBM_TAG_WALL0);
+                                    C cu = C(0);
+                                    if constexpr (Vi::x != 0) cu += C(Vi::x) * (C)uw[0];
+                                    if constexpr (Vi::y != 0) cu += C(Vi::y) * (C)uw[1];
+                                    if constexpr (Vi::z != 0) cu += C(Vi::z) * (C)uw[2];
+                                    hs[e][i] -= C(6.0 * Vi::w) * (C)p.rho0 * cu;
+                                }
+                            }
+                        }
+                    });
+                }
+            }
+        }
+
+        // ---- push
         sfor<Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
             using Vi = V<Q, i>;
-            drho += h[i];
-            if constexpr (Vi::x == 1) jx += h[i];
-            if constexpr (Vi::x == -1) jx -= h[i];
-            if constexpr (Vi::y == 1) jy += h[i];
-            if constexpr (Vi::y == -1) jy -= h[i];
-            if constexpr (Vi::z == 1) jz += h[i];
-            if constexpr (Vi::z == -1) jz -= h[i];
-        });
-        const C Fx = (C)p.force[0], Fy = (C)p.force[1], Fz = (C)p.force[2];
-        const C rho = (C)p.rho0 + drho;
-        const C inv_rho = C(1) / rho;
-        const C ux = (jx + C(0.5) * Fx) * inv_rho;
-        const C uy = (jy + C(0.5) * Fy) * inv_rho;
-        const C uz = (jz + C(0.5) * Fz) * inv_rho;
-        const C uu = ux * ux + uy * uy + uz * uz;
-        const C uF = ux * Fx + uy * Fy + uz * Fz;
-
-        // ---- equilibrium, even/odd parts per pair k = 1..H (direction k, opp k+H)
-        C ev[H + 1], od[H + 1], cuk[H + 1];
-        ev[0] = C(V<Q, 0>::w) * (drho - C(1.5) * rho * uu);
-        od[0] = C(0);
-        cuk[0] = C(0);
-        sfor<H>([&](auto K) {
-            constexpr int k = decltype(K)::value + 1;
-            using Vk = V<Q, k>;
-            C cu = C(0);
-            if constexpr (Vk::x != 0) cu += C(Vk::x) * ux;
-            if constexpr (Vk::y != 0) cu += C(Vk::y) * uy;
-            if constexpr (Vk::z != 0) cu += C(Vk::z) * uz;
-            cuk[k] = cu;
-            ev[k] = C(Vk::w) * (drho + rho * (C(4.5) * cu * cu - C(1.5) * uu));
-            od[k] = C(Vk::w) * C(3) * rho * cu;
-        });
-
-        // ---- relaxation rates from the node's model
-        C wp = (C)p.omega, wm = (C)p.omega;
-        if constexpr ((MS & MS_TRT) != 0) {
-            if (tag == LBM_TAG_TRT) wm = (C)p.omega_minus;
-        }
-        if constexpr ((MS & (MS_SMAG | MS_MLP)) != 0) {
-            // Non-equilibrium momentum flux Pi_ab = sum c_a c_b (h - heq): only
-            // even parts contribute, 2 sum_k c_a c_b (h+_k - ev_k).
-            C pxx = C(0), pyy = C(0), pzz = C(0), pxy = C(0), pxz = C(0), pyz = C(0);
-            sfor<H>([&](auto K) {
-                constexpr int k = decltype(K)::value + 1;
-                using Vk = V<Q, k>;
-                const C ne = (h[k] + h[k + H]) - C(2) * ev[k];
-                if constexpr (Vk::x != 0) pxx += ne;
-                if constexpr (Vk::y != 0) pyy += ne;
-                if constexpr (Vk::z != 0) pzz += ne;
-                if constexpr (Vk::x * Vk::y != 0) pxy += C(Vk::x * Vk::y) * ne;
-                if constexpr (Vk::x * Vk::z != 0) pxz += C(Vk::x * Vk::z) * ne;
-                if constexpr (Vk::y * Vk::z != 0) pyz += C(Vk::y * Vk::z) * ne;
-            });
-            const C qn = sqrt(pxx * pxx + pyy * pyy + pzz * pzz + C(2) * (pxy * pxy + pxz * pxz + pyz * pyz));
-            const C tau0 = (C)p.tau;
-            const C tau_s = C(0.5) * (tau0 + sqrt(tau0 * tau0 + (C)p.smag_c * qn * inv_rho));
-            C tau_eff = tau_s;
-            if constexpr ((MS & MS_MLP) != 0) {
-                const bool want = live && tag == LBM_TAG_BGK_MLP;
-                if (p.has_mlp && __any(want)) {
-                    const float feat[7] = {(float)pxx, (float)pyy, (float)pzz, (float)pxy,
-                                           (float)pxz, (float)pyz, (float)rho};
-                    const float sp = mlp_wave_eval(p.mlp, feat);
-                    const C nu0 = (C)p.nu0;
-                    const C nut = nu0 * (C)sp;
-                    if (isfinite(nut) && nut <= C(10) * nu0) {
-                        if (tag == LBM_TAG_BGK_MLP) tau_eff = C(3) * (nu0 + nut) + C(0.5);
-                    }
-                }
-            }
-            if (tag == LBM_TAG_BGK_SMAG || tag == LBM_TAG_BGK_MLP) {
-                wp = C(1) / tau_eff;
-                wm = wp;
-            }
-        }
-
-        // ---- collide (pair form) and push
-        C hs[Q];
-        {
-            const C gp = C(1) - C(0.5) * wp, gm = C(1) - C(0.5) * wm;
-            const C F0 = C(V<Q, 0>::w) * C(-3) * uF;
-            hs[0] = h[0] - wp * (h[0] - ev[0]) + gp * F0;
-            sfor<H>([&](auto K) {
-                constexpr int k = decltype(K)::value + 1;
-                using Vk = V<Q, k>;
-                C cF = C(0);
-                if constexpr (Vk::x != 0) cF += C(Vk::x) * Fx;
-                if constexpr (Vk::y != 0) cF += C(Vk::y) * Fy;
-                if constexpr (Vk::z != 0) cF += C(Vk::z) * Fz;
-                const C Fe = C(Vk::w) * (C(9) * cuk[k] * cF - C(3) * uF);
-                const C Fo = C(Vk::w) * C(3) * cF;
-                const C hp = C(0.5) * (h[k] + h[k + H]);
-                const C hm = C(0.5) * (h[k] - h[k + H]);
-                const C A = gp * Fe - wp * (hp - ev[k]);
-                const C B = gm * Fo - wm * (hm - od[k]);
-                hs[k] = h[k] + A + B;
-                hs[k + H] = h[k + H] + A - B;
-            });
-        }
-
-        if (live) {
-            sfor<Q>([&](auto I) {
-                constexpr int i = decltype(I)::value;
-                using Vi = V<Q, i>;
-                C v = hs[i];
-                long long off;
-                if constexpr (i == 0) {
-                    off = n;
-                } else if constexpr (PARITY == 0) {
-                    off = (long long)Vi::opp * st + n;
+            S out[VN];
+#pragma unroll
+            for (int e = 0; e < VN; ++e) out[e] = (S)hs[e][i];
+            if constexpr (PARITY == 0 || i == 0) {
+                // even step: h*_i goes to slot opp(i) of the node itself
+                S *dst = f + (long long)Vi::opp * st + row_own;
+                if (all_live) {
+                    vstore<VN>(dst + xb, out);
                 } else {
-                    const int dst = zo[1 + Vi::z] + yo[1 + Vi::y] + xo[1 + Vi::x];
-                    off = (long long)i * st + dst;
-                    if constexpr (TAGGED) {
-                        if ((wall >> i) & 1u) off = (long long)Vi::opp * st + n;
+#pragma unroll
+                    for (int e = 0; e < VN; ++e)
+                        if (live[e]) dst[xn[e][1]] = out[e];
+                }
+            } else {
+                // odd step: h*_i goes to slot i of x + c_i, or back to slot opp(i)
+                // of the node itself when x + c_i is a wall
+                S *nb = f + (long long)i * st + zo[1 + Vi::z] + yo[1 + Vi::y];
+                S *own = f + (long long)Vi::opp * st + row_own;
+                const int start = xb + Vi::x;
+                const bool wall_hit = TAGGED && ((wall_any >> i) & 1u);
+                if (all_live && !wall_hit && start >= 0 && start + VN <= nx) {
+                    vstore<VN>(nb + start, out);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < VN; ++e) {
+                        if (!live[e]) continue;
+                        const bool wb = TAGGED && ((wall[e] >> i) & 1u);
+                        if (wb)
+                            own[xn[e][1]] = out[e];
+                        else
+                            nb[xn[e][1 + Vi::x]] = out[e];
                     }
                 }
-                if constexpr (TAGGED) {
-                    if ((wall >> i) & 1u) {
-                        const int t = s_tag[cidx + (Vi::z * WY + Vi::y) * WX + Vi::x];
-                        if (t >= LBM_TAG_WALL0) {
-                            const double *uw = p.wall_u + 3 * (t - LBM_TAG_WALL0);
-                            C cu = C(0);
-                            if constexpr (Vi::x != 0) cu += C(Vi::x) * (C)uw[0];
-                            if constexpr (Vi::y != 0) cu += C(Vi::y) * (C)uw[1];
-                            if constexpr (Vi::z != 0) cu += C(Vi::z) * (C)uw[2];
-                            v -= C(6.0 * Vi::w) * (C)p.rho0 * cu;
-                        }
-                    }
-                }
-                f[off] = (S)v;
-            });
-        }
+            }
+        });
     }
 
     // ---- per-tile reduction partials (fixed order: shuffle tree, then waves 0..3)
@@ -427,22 +534,28 @@ __global__ __launch_bounds__(256) void k_scatter(AuxParams a) {
 
 // ------------------------------------------------------------- launchers
 
-template <int Q, int P, int MS, bool TG, int MODE>
+template <int Q, int P, int MS, bool TG, int MODE, int VN>
 static hipError_t launch_step_par(const StepParams &p, int parity, hipStream_t s) {
     const dim3 grid(8 * p.tiles_per_xcd), block(256);
     if (parity == 0)
-        k_collide_stream<Q, P, MS, TG, MODE, 0><<<grid, block, 0, s>>>(p);
+        k_collide_stream<Q, P, MS, TG, MODE, 0, VN><<<grid, block, 0, s>>>(p);
     else
-        k_collide_stream<Q, P, MS, TG, MODE, 1><<<grid, block, 0, s>>>(p);
+        k_collide_stream<Q, P, MS, TG, MODE, 1, VN><<<grid, block, 0, s>>>(p);
     return hipGetLastError();
+}
+
+template <int Q, int P, int MS, bool TG, int MODE>
+static hipError_t launch_step_vn(const StepParams &p, int parity, hipStream_t s) {
+    return p.vn == 2 ? launch_step_par<Q, P, MS, TG, MODE, 2>(p, parity, s)
+                     : launch_step_par<Q, P, MS, TG, MODE, 1>(p, parity, s);
 }
 
 template <int Q, int P, int MS, bool TG>
 static hipError_t launch_step_mode(const StepParams &p, int mode, int parity, hipStream_t s) {
     switch (mode) {
-        case MODE_STEP: return launch_step_par<Q, P, MS, TG, MODE_STEP>(p, parity, s);
-        case MODE_STEP_REDUCE: return launch_step_par<Q, P, MS, TG, MODE_STEP_REDUCE>(p, parity, s);
-        default: return launch_step_par<Q, P, MS_BGK, TG, MODE_REDUCE>(p, parity, s);
+        case MODE_STEP: return launch_step_vn<Q, P, MS, TG, MODE_STEP>(p, parity, s);
+        case MODE_STEP_REDUCE: return launch_step_vn<Q, P, MS, TG, MODE_STEP_REDUCE>(p, parity, s);
+        default: return launch_step_vn<Q, P, MS_BGK, TG, MODE_REDUCE>(p, parity, s);
     }
 }
 

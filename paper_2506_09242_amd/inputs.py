@@ -177,3 +177,16 @@ def mlp_he_init(seed: int) -> np.ndarray:
     W3 = z[1248:1280] * np.sqrt(2.0 / 32.0)
     p = np.concatenate([W1, np.zeros(32), W2, np.zeros(32), W3, np.zeros(1), np.zeros(7), np.ones(7)])
     return p.astype(np.float32)
+
+
+def permutation_by_keys(n: int, seed: int) -> np.ndarray:
+    """Random permutation of 0..n-1 by sorting SplitMix64 keys (ties by index).
+    Used where a Python-level Fisher-Yates loop over millions of items is too slow."""
+    return np.argsort(splitmix64(seed, n), kind="stable").astype(np.int64)
+
+
+def sample_without_replacement(pool: int, k: int, seed: int) -> np.ndarray:
+    """k distinct indices of range(pool): the k smallest SplitMix64 keys, in key order."""
+    keys = splitmix64(seed, pool)
+    idx = np.argpartition(keys, k - 1)[:k]
+    return idx[np.argsort(keys[idx], kind="stable")].astype(np.int64)

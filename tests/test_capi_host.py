@@ -122,3 +122,4 @@ def test_header_compiles_as_c():
     """The header is plain C (no C++ constructs)."""
     r = subprocess.run(["gcc", "-std=c99", "-fsyntax-only", "-x", "c", HEADER], capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
+
