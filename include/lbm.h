@@ -139,10 +139,9 @@ lbm_status lbm_create_on_buffer(const lbm_config *cfg, const uint8_t *tags_host,
 void lbm_destroy(lbm_lattice *lat);
 
 /* Override the launch geometry: 256-thread blocks updating tiles of tx x ty
- * nodes of one z-plane, with tx*ty == 256 (one node per thread) or 512 (two
- * consecutive nodes per thread, vector accesses); tx divided by the nodes
- * per thread must be 32, 64, 128 or 256.  Results are bitwise independent of
- * the choice; this exists for tuning and for that test.  EINVAL otherwise. */
+ * nodes of one z-plane, one node per thread (tx in {32,64,128,256},
+ * tx*ty == 256).  Results are bitwise independent of the choice; this exists
+ * for tuning and for that test.  EINVAL for other shapes. */
 lbm_status lbm_set_launch(lbm_lattice *lat, int tx, int ty);
 
 /* ---------------------------------------------------------- initial state */

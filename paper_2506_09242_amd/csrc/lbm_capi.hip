@@ -46,6 +46,7 @@ struct lbm_lattice {
     long long max_tiles = 0;
     double *d_stage1 = nullptr;     // [NRED][kFinalizeBlocks]
     uint8_t *d_tile_tag = nullptr;  // [max_tiles] tile classification of the current tiling
+    uint32_t *d_mask = nullptr;     // [N] neighbour masks (tagged lattices)
     double *d_series = nullptr;     // [series_cap][NRED]
     long long series_cap = 0;
     void *d_mlp = nullptr;          // packed closure block (lbm_mlp.hip)
@@ -56,8 +57,7 @@ struct lbm_lattice {
     int ms = MS_BGK;                // compiled model set
     bool tagged = true;
     int uniform_tag = LBM_TAG_BGK;
-    int tx_log2 = 8;                // log2(threads per tile row)
-    int vn = 1;                     // nodes per thread
+    int tx_log2 = 8;
     int tiles_x = 1, tiles_y = 1, n_tiles = 1;
     long long n_fluid = 0;
     bool failed = false;
@@ -140,25 +140,20 @@ lbm_status validate(const lbm_config *c) {
     return LBM_OK;
 }
 
-void choose_tiles(lbm_lattice *L, int txl, int vn) {
+void choose_tiles(lbm_lattice *L, int txl) {
     L->tx_log2 = txl;
-    L->vn = vn;
-    const int TX = (1 << txl) * vn, TY = 256 >> txl;
+    const int TX = 1 << txl, TY = 256 >> txl;
     L->tiles_x = (L->cfg.nx + TX - 1) / TX;
     L->tiles_y = (L->cfg.ny + TY - 1) / TY;
     L->n_tiles = L->tiles_x * L->tiles_y * L->cfg.nz;
 }
 
-// Nodes per thread by storage precision (wider accesses for narrow types).
-int default_vn(int prec) { return prec == LBM_F64 ? 1 : 2; }
-
-// Default threads per tile row: the smallest padded row (ceil(nx/TX)*TX with
-// TX = vn << txl), larger tiles on ties.
-int default_txl(int nx, int vn) {
+// Default tile width: the smallest padded row (ceil(nx/tx)*tx), larger tx on ties.
+int default_txl(int nx) {
     int best = 8;
-    long long best_pad = (long long)((nx + 256 * vn - 1) / (256 * vn)) * 256 * vn;
+    long long best_pad = (long long)((nx + 255) / 256) * 256;
     for (int l = 7; l >= 5; --l) {
-        const int tx = (1 << l) * vn;
+        const int tx = 1 << l;
         const long long pad = (long long)((nx + tx - 1) / tx) * tx;
         if (pad < best_pad) {
             best_pad = pad;
@@ -186,7 +181,7 @@ StepParams step_params(const lbm_lattice *L) {
     p.n_tiles = L->n_tiles;
     p.tiles_per_xcd = (L->n_tiles + 7) / 8;
     p.tx_log2 = L->tx_log2;
-    p.vn = L->vn;
+    p.mask = L->d_mask;
     p.uniform_tag = L->uniform_tag;
     p.has_force = (c.force[0] != 0.0 || c.force[1] != 0.0 || c.force[2] != 0.0) ? 1 : 0;
     p.has_mlp = L->has_mlp ? 1 : 0;
@@ -281,7 +276,7 @@ __global__ __launch_bounds__(256) void k_tile_classify(StepParams p, uint8_t *ou
     __shared__ int s_first, s_same;
     const int L = blockIdx.x;
     const int txl = p.tx_log2;
-    const int TX = (1 << txl) * p.vn, TY = 256 >> txl;
+    const int TX = 1 << txl, TY = 256 >> txl;
     const int tix = L % p.tiles_x, rem = L / p.tiles_x;
     const int tiy = rem % p.tiles_y, z = rem / p.tiles_y;
     const int x0 = tix * TX, y0 = tiy * TY;
@@ -382,10 +377,7 @@ static lbm_status create_impl(const lbm_config *cfg, const uint8_t *tags_host, v
     L->ms = ms;
     L->tagged = tagged;
     L->uniform_tag = only;
-    {
-        const int vn = default_vn(cfg->prec);
-        choose_tiles(L, default_txl(cfg->nx, vn), vn);
-    }
+    choose_tiles(L, default_txl(cfg->nx));
     static const char *msname[] = {"bgk", "trt", "bgk+smag", "bgk+smag+mlp", "all"};
     int msi = 0;
     for (int k = 0; k < kNumModelSets; ++k)
@@ -426,11 +418,10 @@ static lbm_status create_impl(const lbm_config *cfg, const uint8_t *tags_host, v
     }
     // Partials sized for the tiling with the most tiles over every allowed tile width.
     long long max_tiles = 0;
-    for (int vn = 1; vn <= 2; ++vn)
-        for (int l = 5; l <= 8; ++l) {
-            const long long tx = (1LL << l) * vn, ty = 256 >> l;
-            max_tiles = std::max(max_tiles, ((cfg->nx + tx - 1) / tx) * ((cfg->ny + ty - 1) / ty) * cfg->nz);
-        }
+    for (int l = 5; l <= 8; ++l) {
+        const long long tx = 1LL << l, ty = 256 >> l;
+        max_tiles = std::max(max_tiles, ((cfg->nx + tx - 1) / tx) * ((cfg->ny + ty - 1) / ty) * cfg->nz);
+    }
     L->max_tiles = max_tiles;
     e = hipMalloc(&L->d_partials, (size_t)max_tiles * NRED * sizeof(double));
     if (e != hipSuccess) {
@@ -450,9 +441,20 @@ static lbm_status create_impl(const lbm_config *cfg, const uint8_t *tags_host, v
         L->d_tile_tag = nullptr;
         return bail(set_err(LBM_ENOMEM, "hipMalloc of tile classes failed"));
     }
+    if (tagged) {
+        e = hipMalloc(&L->d_mask, (size_t)N * sizeof(uint32_t));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            L->d_mask = nullptr;
+            return bail(set_err(LBM_ENOMEM, "hipMalloc of neighbour masks failed"));
+        }
+    }
     e = hipMemcpyAsync(L->d_tags, tags_host, (size_t)N, hipMemcpyHostToDevice, L->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(L->d_wall, cfg->wall_velocity, 16 * 3 * sizeof(double), hipMemcpyHostToDevice, L->stream);
+    if (e == hipSuccess && L->tagged)
+        e = cfg->q == 19 ? launch_build_mask<19>(L->d_tags, cfg->nx, cfg->ny, cfg->nz, L->d_mask, L->stream)
+                         : launch_build_mask<27>(L->d_tags, cfg->nx, cfg->ny, cfg->nz, L->d_mask, L->stream);
     if (e == hipSuccess && L->tagged) e = launch_tile_classify(step_params(L), L->d_tile_tag, L->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
     if (e != hipSuccess) return bail(lbmd_fail_hip(nullptr, e, "tag upload"));
@@ -482,6 +484,7 @@ extern "C" void lbm_destroy(lbm_lattice *lat) {
     if (lat->d_partials) (void)hipFree(lat->d_partials);
     if (lat->d_stage1) (void)hipFree(lat->d_stage1);
     if (lat->d_tile_tag) (void)hipFree(lat->d_tile_tag);
+    if (lat->d_mask) (void)hipFree(lat->d_mask);
     if (lat->d_series) (void)hipFree(lat->d_series);
     lbmd_free_mlp(lat);
     delete lat;
@@ -489,15 +492,11 @@ extern "C" void lbm_destroy(lbm_lattice *lat) {
 
 extern "C" lbm_status lbm_set_launch(lbm_lattice *lat, int tx, int ty) {
     CHECK_HANDLE(lat);
-    const int vn = (tx > 0 && ty > 0) ? tx * ty / 256 : 0;
     int l = -1;
-    if ((vn == 1 || vn == 2) && tx * ty == 256 * vn)
-        for (int k = 5; k <= 8; ++k)
-            if (tx == (1 << k) * vn) l = k;
-    if (l < 0)
-        return set_err(LBM_EINVAL, "tile must have tx*ty = 256 (one node per thread) or 512 (two), "
-                                   "tx / (tx*ty/256) in {32, 64, 128, 256}");
-    choose_tiles(lat, l, vn);
+    for (int k = 5; k <= 8; ++k)
+        if (tx == (1 << k)) l = k;
+    if (l < 0 || tx * ty != 256) return set_err(LBM_EINVAL, "tile must be tx in {32,64,128,256} with tx*ty = 256");
+    choose_tiles(lat, l);
     if (lat->tagged) HIPCHK(lat, launch_tile_classify(step_params(lat), lat->d_tile_tag, lat->stream));
     return LBM_OK;
 }

@@ -58,7 +58,8 @@ struct StepParams {
     void *pops;               // population array, Q slots of `stride` elements
     const uint8_t *tags;      // device tags (TAGGED variants)
     const uint8_t *tile_tag;  // per tile: the single fluid tag of the tile and its
-                              // one-node halo, or 0 if the tile needs its tag tile
+                              // one-node halo, or 0 if its nodes read `mask`
+    const uint32_t *mask;     // per-node neighbour mask (TAGGED variants)
     const double *wall_u;     // [16][3] moving-wall velocities (device)
     double *partials;         // [NRED][partial_stride] per-tile reduction partials
     long long stride;         // elements per population slot (padded plane)
@@ -67,8 +68,7 @@ struct StepParams {
     int tiles_x, tiles_y;     // tile grid in x and y (z: one plane per tile row)
     int n_tiles;              // tiles_x * tiles_y * nz
     int tiles_per_xcd;        // ceil(n_tiles / 8)
-    int tx_log2;              // log2(threads per tile row); tile height = 256 >> tx_log2
-    int vn;                   // consecutive nodes per thread (1 or 2); tile width = vn << tx_log2
+    int tx_log2;              // tile width = 1 << tx_log2, height = 256 >> tx_log2
     int uniform_tag;          // model tag of every node (untagged variants)
     int has_force;
     int has_mlp;              // closure parameters uploaded
@@ -105,6 +105,8 @@ enum GatherMode : int { G_POPS = 0, G_FIELDS = 1, G_CELLS = 2 };
 
 template <int Q, int P>
 hipError_t launch_step(const StepParams &p, int ms, bool tagged, int mode, int parity, hipStream_t s);
+template <int Q>
+hipError_t launch_build_mask(const uint8_t *tags, int nx, int ny, int nz, uint32_t *mask, hipStream_t s);
 template <int Q, int P>
 hipError_t launch_init(const AuxParams &a, hipStream_t s);
 template <int Q, int P>

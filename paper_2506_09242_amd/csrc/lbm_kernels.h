@@ -40,21 +40,14 @@
 
 namespace lbmd {
 
-// Largest tag tile staged in LDS: (TX+2)*(TY+2)*3 bytes, TX = cells per tile
-// row (threads per row x nodes per thread), TY = rows; worst case TX = 512, TY = 1.
-constexpr int kTileBytes = 4640;
+// Per-node neighbour mask layout: bits 0..26 wall bits (bit i set when node
+// x + c_i is not fluid), bit 27 set when a neighbour is a moving wall, bits
+// 28..31 the node's own fluid tag (0 for a non-fluid node).
+constexpr uint32_t kMaskWalls = (1u << 27) - 1u;
+constexpr int kMaskMovingBit = 27;
+constexpr int kMaskTagShift = 28;
 
 __device__ __forceinline__ int wrap_idx(int v, int n) { return v < 0 ? v + n : (v >= n ? v % n : v); }
-
-// V consecutive elements of one slot (a single, possibly unaligned, vector access).
-template <int V, typename S>
-__device__ __forceinline__ void vload(S (&d)[V], const S *p) {
-    __builtin_memcpy(d, p, sizeof(S) * V);
-}
-template <int V, typename S>
-__device__ __forceinline__ void vstore(S *p, const S (&d)[V]) {
-    __builtin_memcpy(p, d, sizeof(S) * V);
-}
 
 // FP64 reduction terms of one node's loaded (time-t) populations, added to red.
 template <int Q, typename C>
@@ -193,12 +186,11 @@ __device__ __forceinline__ void collide_node(const C (&h)[Q], int tag, bool live
     });
 }
 
-// The fused collide-and-stream step.  Each thread updates VN consecutive
-// nodes of one row; a tile is (threads per row * VN) x (256 / threads per
-// row) nodes of one z-plane.  Accesses of the VN nodes to one slot are a
-// single vector load/store unless a wall, a periodic wrap or a ragged row
-// end splits them.
-template <int Q, int P, int MS, bool TAGGED, int MODE, int PARITY, int VN>
+// The fused collide-and-stream step: one thread per node, 256-thread blocks
+// covering a tile of (1 << tx_log2) x (256 >> tx_log2) nodes of one z-plane.
+// Wall handling selects addresses (never branches around a load or store),
+// so the Q loads of a thread are all in flight together.
+template <int Q, int P, int MS, bool TAGGED, int MODE, int PARITY>
 __global__ __launch_bounds__(256) void k_collide_stream(StepParams p) {
     using S = typename Prec<P>::S;
     using C = typename Prec<P>::C;
@@ -210,209 +202,132 @@ __global__ __launch_bounds__(256) void k_collide_stream(StepParams p) {
     const int L = (wg & 7) * p.tiles_per_xcd + (wg >> 3);
     if (L >= p.n_tiles) return;  // uniform for the block
 
-    const int txl = p.tx_log2;            // log2(threads per tile row)
-    const int TXT = 1 << txl, TY = 256 >> txl;
-    const int TX = TXT * VN;              // nodes per tile row
+    const int txl = p.tx_log2;
+    const int TX = 1 << txl, TY = 256 >> txl;
     const int tix = L % p.tiles_x;
     const int rem = L / p.tiles_x;
     const int tiy = rem % p.tiles_y;
     const int z = rem / p.tiles_y;
-    const int lx = threadIdx.x & (TXT - 1), ly = threadIdx.x >> txl;
-    const int x0 = tix * TX, y0 = tiy * TY;
-    const int xb = x0 + VN * lx, y = y0 + ly;
+    const int lx = threadIdx.x & (TX - 1), ly = threadIdx.x >> txl;
+    const int x = (tix << txl) + lx, y = tiy * TY + ly;
     const int nx = p.nx, ny = p.ny, nz = p.nz;
-    const bool row_ok = y < ny;
+    const bool active = (x < nx) && (y < ny);
 
-    int tag[VN];
-    uint32_t wall[VN];  // bit i: node x + c_i is not fluid
-    bool act[VN];
-#pragma unroll
-    for (int e = 0; e < VN; ++e) {
-        tag[e] = p.uniform_tag;
-        wall[e] = 0;
-        act[e] = row_ok && (xb + e < nx);
-    }
-    __shared__ uint8_t s_tag[TAGGED ? kTileBytes : 1];
-    const int WX = TX + 2, WY = TY + 2;
-    const int cidx = (WY + ly + 1) * WX + VN * lx + 1;  // centre of node 0 in the tag tile
+    // Neighbour offsets with periodic wrap; index 1 + c for c in {-1, 0, 1}.
+    const int xc = active ? x : 0, yc = active ? y : 0;
+    const int xo[3] = {xc == 0 ? nx - 1 : xc - 1, xc, xc + 1 == nx ? 0 : xc + 1};
+    const int yo[3] = {(yc == 0 ? ny - 1 : yc - 1) * nx, yc * nx, (yc + 1 == ny ? 0 : yc + 1) * nx};
+    const int nxy = nx * ny;
+    const int zo[3] = {(z == 0 ? nz - 1 : z - 1) * nxy, z * nxy, (z + 1 == nz ? 0 : z + 1) * nxy};
+    const int n = zo[1] + yo[1] + xo[1];
+
+    // Node class.  Tiles whose one-node halo is a single fluid model (the
+    // interior of a walled domain) need nothing; other tiles read the node's
+    // precomputed neighbour mask (block-uniform branch).
+    int tag = p.uniform_tag;
+    uint32_t wall = 0;   // bit i: node x + c_i is not fluid
+    bool moving = false; // some neighbour is a moving wall
     if constexpr (TAGGED) {
-        // Tiles whose one-node halo holds a single fluid model (the interior of a
-        // walled domain) skip the tag tile; the branch is uniform per block.
         const int tile_tag = p.tile_tag[L];
         if (tile_tag != 0) {
-#pragma unroll
-            for (int e = 0; e < VN; ++e) tag[e] = tile_tag;
+            tag = tile_tag;
         } else {
-            const int total = WX * WY * 3;
-            for (int k = threadIdx.x; k < total; k += 256) {
-                const int ax = k % WX;
-                const int r = k / WX;
-                const int ay = r % WY;
-                const int az = r / WY;
-                const int gx = wrap_idx(x0 + ax - 1, nx);
-                const int gy = wrap_idx(y0 + ay - 1, ny);
-                const int gz = wrap_idx(z + az - 1, nz);
-                s_tag[k] = p.tags[((long long)gz * ny + gy) * nx + gx];
-            }
-            __syncthreads();
-#pragma unroll
-            for (int e = 0; e < VN; ++e) {
-                tag[e] = s_tag[cidx + e];
-                sfor<Q>([&](auto I) {
-                    constexpr int i = decltype(I)::value;
-                    if constexpr (i > 0) {
-                        using Vi = V<Q, i>;
-                        const int t = s_tag[cidx + e + (Vi::z * WY + Vi::y) * WX + Vi::x];
-                        if (!is_fluid_tag(t)) wall[e] |= 1u << i;
-                    }
-                });
-            }
+            const uint32_t m = active ? p.mask[n] : 0u;
+            wall = m & kMaskWalls;
+            moving = (m >> kMaskMovingBit) & 1u;
+            tag = (int)(m >> kMaskTagShift);
         }
     }
-    bool live[VN];
-    bool all_act = true, all_live = true;
-    uint32_t wall_any = 0;
-#pragma unroll
-    for (int e = 0; e < VN; ++e) {
-        live[e] = act[e] && (!TAGGED || is_fluid_tag(tag[e]));
-        all_act = all_act && act[e];
-        all_live = all_live && live[e];
-        wall_any |= wall[e];
-    }
+    const bool live = active && (!TAGGED || tag != 0);
 
-    // Row offsets (periodic) and x of each node with its +-1 neighbours.
-    const int yc = row_ok ? y : 0;
-    const int nxy = nx * ny;
-    const int yo[3] = {(yc == 0 ? ny - 1 : yc - 1) * nx, yc * nx, (yc + 1 == ny ? 0 : yc + 1) * nx};
-    const int zo[3] = {(z == 0 ? nz - 1 : z - 1) * nxy, z * nxy, (z + 1 == nz ? 0 : z + 1) * nxy};
-    int xn[VN][3];
-#pragma unroll
-    for (int e = 0; e < VN; ++e) {
-        const int xe = act[e] ? xb + e : 0;
-        xn[e][0] = xe == 0 ? nx - 1 : xe - 1;
-        xn[e][1] = xe;
-        xn[e][2] = xe + 1 == nx ? 0 : xe + 1;
-    }
-    const int row_own = zo[1] + yo[1];
     const long long st = p.stride;
     S *__restrict__ f = static_cast<S *>(p.pops);
 
-    // ---- pull the nodes' populations
-    C h[VN][Q];
-    sfor<Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        using Vi = V<Q, i>;
-        if constexpr (PARITY == 0 || i == 0) {
-            const S *src = f + (long long)i * st + row_own;
-            if (all_act) {
-                S tmp[VN];
-                vload<VN>(tmp, src + xb);
-#pragma unroll
-                for (int e = 0; e < VN; ++e) h[e][i] = (C)tmp[e];
+    // ---- pull the node's populations
+    C h[Q];
+    if (live) {
+        sfor<Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            using Vi = V<Q, i>;
+            long long off;
+            if constexpr (PARITY == 0 || i == 0) {
+                off = (long long)i * st + n;
             } else {
-#pragma unroll
-                for (int e = 0; e < VN; ++e) h[e][i] = act[e] ? (C)src[xn[e][1]] : C(0);
-            }
-        } else {
-            // direction i arrives from x - c_i (slot opp), or from the node's own
-            // slot i when x - c_i is a wall
-            const S *nb = f + (long long)Vi::opp * st + zo[1 - Vi::z] + yo[1 - Vi::y];
-            const S *own = f + (long long)i * st + row_own;
-            const int start = xb - Vi::x;
-            const bool wall_hit = TAGGED && ((wall_any >> Vi::opp) & 1u);
-            if (all_act && !wall_hit && start >= 0 && start + VN <= nx) {
-                S tmp[VN];
-                vload<VN>(tmp, nb + start);
-#pragma unroll
-                for (int e = 0; e < VN; ++e) h[e][i] = (C)tmp[e];
-            } else {
-#pragma unroll
-                for (int e = 0; e < VN; ++e) {
-                    const bool wb = TAGGED && ((wall[e] >> Vi::opp) & 1u);
-                    h[e][i] = act[e] ? (C)(wb ? own[xn[e][1]] : nb[xn[e][1 - Vi::x]]) : C(0);
+                // direction i arrives from x - c_i (slot opp), or from the node's
+                // own slot i when x - c_i is a wall
+                const int src = zo[1 - Vi::z] + yo[1 - Vi::y] + xo[1 - Vi::x];
+                const long long o_nb = (long long)Vi::opp * st + src;
+                if constexpr (TAGGED) {
+                    const bool wb = (wall >> Vi::opp) & 1u;
+                    off = wb ? (long long)i * st + n : o_nb;
+                } else {
+                    off = o_nb;
                 }
             }
-        }
-    });
+            h[i] = (C)f[off];
+        });
+    } else {
+        sfor<Q>([&](auto I) { h[decltype(I)::value] = C(0); });
+    }
 
     double red[NRED];
     if constexpr (MODE != MODE_STEP) {
 #pragma unroll
         for (int k = 0; k < NRED; ++k) red[k] = 0.0;
-#pragma unroll
-        for (int e = 0; e < VN; ++e) node_reduce<Q, C>(h[e], live[e], p, red);
+        node_reduce<Q, C>(h, live, p, red);
     }
 
     if constexpr (MODE != MODE_REDUCE) {
-        C hs[VN][Q];
-#pragma unroll
-        for (int e = 0; e < VN; ++e) collide_node<Q, C, MS>(h[e], tag[e], live[e], p, hs[e]);
+        C hs[Q];
+        collide_node<Q, C, MS>(h, tag, live, p, hs);
 
-        // moving-wall term where x + c_i is a wall (zero for resting walls)
+        // moving-wall term where x + c_i is a moving wall (nodes next to one only)
         if constexpr (TAGGED) {
-            if (wall_any) {
-#pragma unroll
-                for (int e = 0; e < VN; ++e) {
-                    sfor<Q>([&](auto I) {
-                        constexpr int i = decltype(I)::value;
-                        using Vi = V<Q, i>;
-                        if constexpr (i > 0) {
-                            if ((wall[e] >> i) & 1u) {
-                                const int t = s_tag[cidx + e + (Vi::z * WY + Vi::y) * WX + Vi::x];
-                                if (t >= LBM_TAG_WALL0) {
-                                    const double *uw = p.wall_u + 3 * (t - LBM_TAG_WALL0);
-                                    C cu = C(0);
-                                    if constexpr (Vi::x != 0) cu += C(Vi::x) * (C)uw[0];
-                                    if constexpr (Vi::y != 0) cu += C(Vi::y) * (C)uw[1];
-                                    if constexpr (Vi::z != 0) cu += C(Vi::z) * (C)uw[2];
-                                    hs[e][i] -= C(6.0 * Vi::w) * (C)p.rho0 * cu;
-                                }
+            if (moving) {
+                sfor<Q>([&](auto I) {
+                    constexpr int i = decltype(I)::value;
+                    using Vi = V<Q, i>;
+                    if constexpr (i > 0) {
+                        if ((wall >> i) & 1u) {
+                            const int dst = zo[1 + Vi::z] + yo[1 + Vi::y] + xo[1 + Vi::x];
+                            const int t = p.tags[dst];
+                            if (t >= LBM_TAG_WALL0) {
+                                const double *uw = p.wall_u + 3 * (t - LBM_TAG_WALL0);
+                                C cu = C(0);
+                                if constexpr (Vi::x != 0) cu += C(Vi::x) * (C)uw[0];
+                                if constexpr (Vi::y != 0) cu += C(Vi::y) * (C)uw[1];
+                                if constexpr (Vi::z != 0) cu += C(Vi::z) * (C)uw[2];
+                                hs[i] -= C(6.0 * Vi::w) * (C)p.rho0 * cu;
                             }
                         }
-                    });
-                }
+                    }
+                });
             }
         }
 
         // ---- push
-        sfor<Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            using Vi = V<Q, i>;
-            S out[VN];
-#pragma unroll
-            for (int e = 0; e < VN; ++e) out[e] = (S)hs[e][i];
-            if constexpr (PARITY == 0 || i == 0) {
-                // even step: h*_i goes to slot opp(i) of the node itself
-                S *dst = f + (long long)Vi::opp * st + row_own;
-                if (all_live) {
-                    vstore<VN>(dst + xb, out);
+        if (live) {
+            sfor<Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                using Vi = V<Q, i>;
+                long long off;
+                if constexpr (i == 0) {
+                    off = n;
+                } else if constexpr (PARITY == 0) {
+                    // even step: h*_i goes to slot opp(i) of the node itself
+                    off = (long long)Vi::opp * st + n;
                 } else {
-#pragma unroll
-                    for (int e = 0; e < VN; ++e)
-                        if (live[e]) dst[xn[e][1]] = out[e];
-                }
-            } else {
-                // odd step: h*_i goes to slot i of x + c_i, or back to slot opp(i)
-                // of the node itself when x + c_i is a wall
-                S *nb = f + (long long)i * st + zo[1 + Vi::z] + yo[1 + Vi::y];
-                S *own = f + (long long)Vi::opp * st + row_own;
-                const int start = xb + Vi::x;
-                const bool wall_hit = TAGGED && ((wall_any >> i) & 1u);
-                if (all_live && !wall_hit && start >= 0 && start + VN <= nx) {
-                    vstore<VN>(nb + start, out);
-                } else {
-#pragma unroll
-                    for (int e = 0; e < VN; ++e) {
-                        if (!live[e]) continue;
-                        const bool wb = TAGGED && ((wall[e] >> i) & 1u);
-                        if (wb)
-                            own[xn[e][1]] = out[e];
-                        else
-                            nb[xn[e][1 + Vi::x]] = out[e];
+                    // odd step: h*_i goes to slot i of x + c_i, or back to slot
+                    // opp(i) of the node itself when x + c_i is a wall
+                    const int dst = zo[1 + Vi::z] + yo[1 + Vi::y] + xo[1 + Vi::x];
+                    off = (long long)i * st + dst;
+                    if constexpr (TAGGED) {
+                        if ((wall >> i) & 1u) off = (long long)Vi::opp * st + n;
                     }
                 }
-            }
-        });
+                f[off] = (S)hs[i];
+            });
+        }
     }
 
     // ---- per-tile reduction partials (fixed order: shuffle tree, then waves 0..3)
@@ -432,6 +347,32 @@ __global__ __launch_bounds__(256) void k_collide_stream(StepParams p) {
             p.partials[(long long)k * p.partial_stride + L] = (s_red[0][k] + s_red[1][k]) + (s_red[2][k] + s_red[3][k]);
         }
     }
+}
+
+// Neighbour mask of every node (see kMask*): wall bits, moving-wall flag and
+// the node's own fluid tag (0 for non-fluid nodes).
+template <int Q>
+__global__ __launch_bounds__(256) void k_build_mask(const uint8_t *tags, int nx, int ny, int nz, uint32_t *mask) {
+    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    const long long N = (long long)nx * ny * nz;
+    if (t >= N) return;
+    const int x = (int)(t % nx), y = (int)((t / nx) % ny), z = (int)(t / ((long long)nx * ny));
+    const int own = tags[t];
+    uint32_t m = 0;
+    if (is_fluid_tag(own)) {
+        m = (uint32_t)own << kMaskTagShift;
+        sfor<Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            if constexpr (i > 0) {
+                using Vi = V<Q, i>;
+                const int gx = wrap_idx(x + Vi::x, nx), gy = wrap_idx(y + Vi::y, ny), gz = wrap_idx(z + Vi::z, nz);
+                const int tn = tags[((long long)gz * ny + gy) * nx + gx];
+                if (!is_fluid_tag(tn)) m |= 1u << i;
+                if (tn >= LBM_TAG_WALL0) m |= 1u << kMaskMovingBit;
+            }
+        });
+    }
+    mask[t] = m;
 }
 
 // ------------------------------------------------------------- helpers
@@ -534,28 +475,22 @@ __global__ __launch_bounds__(256) void k_scatter(AuxParams a) {
 
 // ------------------------------------------------------------- launchers
 
-template <int Q, int P, int MS, bool TG, int MODE, int VN>
+template <int Q, int P, int MS, bool TG, int MODE>
 static hipError_t launch_step_par(const StepParams &p, int parity, hipStream_t s) {
     const dim3 grid(8 * p.tiles_per_xcd), block(256);
     if (parity == 0)
-        k_collide_stream<Q, P, MS, TG, MODE, 0, VN><<<grid, block, 0, s>>>(p);
+        k_collide_stream<Q, P, MS, TG, MODE, 0><<<grid, block, 0, s>>>(p);
     else
-        k_collide_stream<Q, P, MS, TG, MODE, 1, VN><<<grid, block, 0, s>>>(p);
+        k_collide_stream<Q, P, MS, TG, MODE, 1><<<grid, block, 0, s>>>(p);
     return hipGetLastError();
-}
-
-template <int Q, int P, int MS, bool TG, int MODE>
-static hipError_t launch_step_vn(const StepParams &p, int parity, hipStream_t s) {
-    return p.vn == 2 ? launch_step_par<Q, P, MS, TG, MODE, 2>(p, parity, s)
-                     : launch_step_par<Q, P, MS, TG, MODE, 1>(p, parity, s);
 }
 
 template <int Q, int P, int MS, bool TG>
 static hipError_t launch_step_mode(const StepParams &p, int mode, int parity, hipStream_t s) {
     switch (mode) {
-        case MODE_STEP: return launch_step_vn<Q, P, MS, TG, MODE_STEP>(p, parity, s);
-        case MODE_STEP_REDUCE: return launch_step_vn<Q, P, MS, TG, MODE_STEP_REDUCE>(p, parity, s);
-        default: return launch_step_vn<Q, P, MS_BGK, TG, MODE_REDUCE>(p, parity, s);
+        case MODE_STEP: return launch_step_par<Q, P, MS, TG, MODE_STEP>(p, parity, s);
+        case MODE_STEP_REDUCE: return launch_step_par<Q, P, MS, TG, MODE_STEP_REDUCE>(p, parity, s);
+        default: return launch_step_par<Q, P, MS_BGK, TG, MODE_REDUCE>(p, parity, s);
     }
 }
 
@@ -577,6 +512,13 @@ hipError_t launch_step(const StepParams &p, int ms, bool tagged, int mode, int p
             return launch_step_geo<Q, P, MS_BGK | MS_TRT | MS_SMAG | MS_MLP>(p, tagged, mode, parity, s);
         default: return hipErrorInvalidValue;
     }
+}
+
+template <int Q>
+hipError_t launch_build_mask(const uint8_t *tags, int nx, int ny, int nz, uint32_t *mask, hipStream_t s) {
+    const long long N = (long long)nx * ny * nz;
+    k_build_mask<Q><<<(unsigned)((N + 255) / 256), 256, 0, s>>>(tags, nx, ny, nz, mask);
+    return hipGetLastError();
 }
 
 template <int Q, int P>
