@@ -217,6 +217,8 @@ def main():
     if "f64" in results:
         ref = results["f64"]
         k_ref = np.array([m["kinetic_energy"] for m in ref["series"]])
+        t_ref = np.array([m["step"] for m in ref["series"]], dtype=np.float64)
+        eps_ref = -np.gradient(k_ref, t_ref) if len(t_ref) > 2 else None
         for pn, r in results.items():
             if pn == "f64":
                 continue
@@ -226,6 +228,23 @@ def main():
                           "k_rel_l2_series": float(np.linalg.norm(k - k_ref) / np.linalg.norm(k_ref)),
                           "u_rel_l2": float(np.linalg.norm(du) / np.linalg.norm(ref["u"])),
                           "u_max_abs": float(np.abs(du).max())}
+            if eps_ref is not None:
+                eps = -np.gradient(k, t_ref)
+                errors[pn]["eps_rel_l2_series"] = float(np.linalg.norm(eps - eps_ref) / np.linalg.norm(eps_ref))
+
+    # derived outputs (host): permeability of the porous case (mean over all
+    # nodes, solids counted as zero velocity), lattice units and millidarcy at
+    # the Berea voxel size 5.345 um
+    derived = {}
+    if args.workload == "porous400_d3q19_trt":
+        nu = (kw["tau"] - 0.5) / 3.0
+        F = kw["force"][0]
+        for pn, r in results.items():
+            ux_mean = r["series"][-1]["velocity_sum"][0] / tags.size
+            k_lu = nu * ux_mean / F
+            derived[pn] = {"permeability_lu": k_lu, "permeability_mD": k_lu * (5.345e-6) ** 2 / 9.869233e-16,
+                           "porosity": float(np.isin(tags, (1, 2, 3, 4)).mean()),
+                           "steps_total": args.warmup + args.steps}
 
     main_p = prec_names[0]
     m = results[main_p]
@@ -251,6 +270,7 @@ def main():
                            if k in ("MLUPS", "MFLUPS_fluid", "ms_per_step", "alg_GBps", "hbm_frac", "variant")}
                       for pn, r in results.items()},
         "error_vs_fp64": errors,
+        "derived": derived,
         "kernel_source_hash": source_hash(),
     }
     print(json.dumps(line), flush=True)

@@ -172,6 +172,15 @@ lbm_status lbm_step_reduce(lbm_lattice *lat, int64_t n_steps, int64_t every, lbm
  * EUNSTABLE if non-finite values were found. */
 lbm_status lbm_reduce(lbm_lattice *lat, lbm_moments *out);
 
+/* Volume-averaged enstrophy of the natural state (Eq. 5, second part):
+ * (1/N) sum over nodes of |w|^2 / 2, w = curl u, each derivative by the
+ * eighth-order centred difference (coefficients 4/5, -1/5, 4/105, -1/280 at
+ * distances 1..4) on the periodic lattice, u from lbm_read_fields' definition.
+ * Needs an all-fluid lattice with every axis >= 9 nodes (EUNSUPPORTED
+ * otherwise; the stencil is undefined across walls).  Uses a temporary device
+ * buffer of 4 doubles per node.  Synchronizes. */
+lbm_status lbm_enstrophy(lbm_lattice *lat, double *out);
+
 /* Wait for all work queued on the handle's stream. */
 lbm_status lbm_synchronize(lbm_lattice *lat);
 

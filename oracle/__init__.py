@@ -166,5 +166,20 @@ def mlp_eddy_viscosity(params, feat, nu0):
                                         np.ascontiguousarray(feat, dtype=np.float64), nu0)
 
 
+def enstrophy(u):
+    """(1/N) sum |curl u|^2 / 2 over a periodic all-fluid lattice, u[3][z][y][x],
+    each derivative by the eighth-order centred difference (Eq. 5)."""
+    a = (4.0 / 5.0, -1.0 / 5.0, 4.0 / 105.0, -1.0 / 280.0)
+
+    def d(f, axis):  # axis in array order (0: z, 1: y, 2: x)
+        return sum(a[j - 1] * (np.roll(f, -j, axis=axis) - np.roll(f, j, axis=axis)) for j in range(1, 5))
+
+    ux, uy, uz = u
+    wx = d(uz, 1) - d(uy, 0)
+    wy = d(ux, 0) - d(uz, 2)
+    wz = d(uy, 2) - d(ux, 1)
+    return float(np.mean(0.5 * (wx * wx + wy * wy + wz * wz)))
+
+
 def num_threads():
     return lib().orc_num_threads()

@@ -304,6 +304,38 @@ hipError_t launch_tile_classify(const StepParams &p, uint8_t *out, hipStream_t s
     return hipGetLastError();
 }
 
+// Enstrophy partials: one block per 256 nodes, |curl u|^2 / 2 with the
+// eighth-order centred difference on the periodic lattice; slot 0 of the
+// reduction layout holds the sum, the other slots are zero.
+__device__ __forceinline__ double d8(const double *u, long long base, long long stride, int c, int n) {
+    auto at = [&](int k) { return u[base + (long long)(((c + k) % n + n) % n) * stride]; };
+    return 0.8 * (at(1) - at(-1)) - 0.2 * (at(2) - at(-2)) + (4.0 / 105.0) * (at(3) - at(-3)) -
+           (1.0 / 280.0) * (at(4) - at(-4));
+}
+
+__global__ __launch_bounds__(256) void k_enstrophy(const double *fields, int nx, int ny, int nz, double *partials,
+                                                   long long pstride) {
+    const long long N = (long long)nx * ny * nz;
+    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    double v = 0.0;
+    if (t < N) {
+        const int x = (int)(t % nx), y = (int)((t / nx) % ny), z = (int)(t / ((long long)nx * ny));
+        const double *ux = fields + N, *uy = fields + 2 * N, *uz = fields + 3 * N;
+        const long long rx = t - x, ry = t - (long long)y * nx, rz = t - (long long)z * nx * ny;
+        const long long sy = nx, sz = (long long)nx * ny;
+        const double wx = d8(uz, ry, sy, y, ny) - d8(uy, rz, sz, z, nz);
+        const double wy = d8(ux, rz, sz, z, nz) - d8(uz, rx, 1, x, nx);
+        const double wz = d8(uy, rx, 1, x, nx) - d8(ux, ry, sy, y, ny);
+        v = 0.5 * (wx * wx + wy * wy + wz * wz);
+    }
+    __shared__ double s[4];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x < NRED)
+        partials[(long long)threadIdx.x * pstride + blockIdx.x] = threadIdx.x == 0 ? (s[0] + s[1]) + (s[2] + s[3]) : 0.0;
+}
+
 hipError_t launch_finalize(const double *partials, long long partial_stride, int n_tiles, double *stage1, double *out,
                            hipStream_t s) {
     const int nb = std::min(kFinalizeBlocks, std::max(1, (n_tiles + 255) / 256));
@@ -776,6 +808,35 @@ static lbm_status scatter_range(lbm_lattice *lat, const double *f_host, int64_t 
     }
     lat->parity = 0;
     lat->t = t;
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_enstrophy(lbm_lattice *lat, double *out) {
+    CHECK_HANDLE(lat);
+    if (!out) return set_err(LBM_EINVAL, "null output");
+    const lbm_config &c = lat->cfg;
+    if (lat->n_fluid != lat->ncell) return set_err(LBM_EUNSUPPORTED, "enstrophy needs an all-fluid lattice");
+    if (c.nx < 9 || c.ny < 9 || c.nz < 9) return set_err(LBM_EUNSUPPORTED, "enstrophy needs every axis >= 9 nodes");
+    const long long N = lat->ncell;
+    const long long nblocks = (N + 255) / 256;
+    DevBuf fields, part, res;
+    HIPCHK(lat, hipMalloc(&fields.p, (size_t)N * 4 * sizeof(double)));
+    HIPCHK(lat, hipMalloc(&part.p, (size_t)nblocks * NRED * sizeof(double)));
+    HIPCHK(lat, hipMalloc(&res.p, NRED * sizeof(double)));
+    AuxParams a = aux_params(lat);
+    a.cell0 = 0;
+    a.count = N;
+    a.out = static_cast<double *>(fields.p);
+    HIPCHK(lat, pick(c.q, c.prec).gather(a, G_FIELDS, lat->stream));
+    k_enstrophy<<<(unsigned)nblocks, 256, 0, lat->stream>>>(static_cast<const double *>(fields.p), c.nx, c.ny, c.nz,
+                                                            static_cast<double *>(part.p), nblocks);
+    HIPCHK(lat, hipGetLastError());
+    HIPCHK(lat, launch_finalize(static_cast<const double *>(part.p), nblocks, (int)nblocks, lat->d_stage1,
+                                static_cast<double *>(res.p), lat->stream));
+    double h[NRED];
+    HIPCHK(lat, hipMemcpyAsync(h, res.p, sizeof h, hipMemcpyDeviceToHost, lat->stream));
+    HIPCHK(lat, hipStreamSynchronize(lat->stream));
+    *out = h[0] / (double)N;
     return LBM_OK;
 }
 

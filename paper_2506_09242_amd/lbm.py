@@ -60,6 +60,7 @@ SIGNATURES = {
     "lbm_step_reduce": (C.c_int, [_P, C.c_int64, C.c_int64, C.POINTER(LbmMoments), C.c_int64]),
     "lbm_reduce": (C.c_int, [_P, C.POINTER(LbmMoments)]),
     "lbm_synchronize": (C.c_int, [_P]),
+    "lbm_enstrophy": (C.c_int, [_P, C.POINTER(C.c_double)]),
     "lbm_time": (C.c_int64, [_P]),
     "lbm_read_fields": (C.c_int, [_P, _P, _P]),
     "lbm_read_populations": (C.c_int, [_P, _P]),
@@ -261,6 +262,11 @@ class Lattice:
             raise LbmError(rc, lbm_last_error())
         _check(rc)
         return m.as_dict()
+
+    def enstrophy(self):
+        v = C.c_double()
+        _check(lib().lbm_enstrophy(self.h, C.byref(v)))
+        return v.value
 
     def synchronize(self):
         _check(lib().lbm_synchronize(self.h))

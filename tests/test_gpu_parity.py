@@ -285,3 +285,23 @@ def test_reduced_precision_error_is_stated(prec, bound):
     e_k = abs(res[prec][1] / res[lbm.LBM_F64][1] - 1.0)
     _print(f"precision {prec}: velocity rel L2 {e_u:.3e}, k rel err {e_k:.3e}")
     assert e_u < bound and e_k < bound
+
+
+def test_enstrophy_vs_oracle():
+    """Eighth-order finite-difference enstrophy (Eq. 5) of a running D3Q27
+    Taylor-Green lattice: GPU vs oracle (on the oracle's own run), 1e-12."""
+    n = 24
+    rho, u = inputs.tgv3d_fields(n, 0.05)
+    tags = inputs.all_fluid(n, n, n, inputs.TAG_SMAG)
+    o, L = make_pair(tags, q=27, tau=0.51, smag_cs=0.1, rho=rho, u=u)
+    L.step(31)
+    o.run(31)
+    _, uo = o.fields()
+    e_o = oracle.enstrophy(uo)
+    e_g = L.enstrophy()
+    _print("enstrophy", e_g, e_o)
+    assert abs(e_g / e_o - 1.0) <= 1e-12
+    walled = lbm.Lattice(inputs.cavity_tags(12), q=19, tau=0.6)
+    with pytest.raises(lbm.LbmError) as e:
+        walled.enstrophy()
+    assert e.value.status == lbm.LBM_EUNSUPPORTED

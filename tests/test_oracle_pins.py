@@ -371,3 +371,31 @@ def test_tgv2d_decay_rate():
     e64 = _tgv2d_rate(64, 0.01, 0.8, 400)
     assert e32 < 2e-2
     assert e32 / e64 >= 3.0
+
+
+def _kmod(k):
+    """Modified wavenumber of the eighth-order centred difference."""
+    a = (4.0 / 5.0, -1.0 / 5.0, 4.0 / 105.0, -1.0 / 280.0)
+    return 2.0 * sum(a[j - 1] * np.sin(j * k) for j in range(1, 5))
+
+
+def test_enstrophy_single_mode():
+    """u_y = a sin(k x): w_z = a k' cos(k x), enstrophy = a^2 k'^2 / 4 exactly."""
+    n, amp = 24, 0.03
+    x = np.arange(n)
+    for m in (1, 3):
+        k = 2 * np.pi * m / n
+        u = np.zeros((3, n, n, n))
+        u[1] = amp * np.sin(k * x)[None, None, :]
+        assert abs(oracle.enstrophy(u) - amp ** 2 * _kmod(k) ** 2 / 4.0) < 1e-15
+
+
+def test_enstrophy_taylor_green():
+    """Taylor-Green field of Eqs. (1)-(4): |w|^2 averages to 3 u0^2 k^2 / 4, so the
+    enstrophy is 3 u0^2 k'^2 / 8 with the stencil's modified wavenumber k'."""
+    n, u0 = 20, 0.05
+    _, u = inputs.tgv3d_fields(n, u0)
+    k = 2 * np.pi / n
+    assert abs(oracle.enstrophy(u) / (3 * u0 * u0 * _kmod(k) ** 2 / 8.0) - 1.0) < 1e-12
+    # and the stencil is accurate: k' = k (1 - O(k^8))
+    assert abs(_kmod(k) / k - 1.0) < 1e-5
