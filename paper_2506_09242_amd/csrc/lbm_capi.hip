@@ -47,6 +47,7 @@ struct lbm_lattice {
     double *d_stage1 = nullptr;     // [NRED][kFinalizeBlocks]
     uint8_t *d_tile_tag = nullptr;  // [max_tiles] tile classification of the current tiling
     uint32_t *d_mask = nullptr;     // [N] neighbour masks (tagged lattices)
+    uint8_t *d_cls = nullptr;       // [N] node classes (tagged lattices)
     double *d_series = nullptr;     // [series_cap][NRED]
     long long series_cap = 0;
     void *d_mlp = nullptr;          // packed closure block (lbm_mlp.hip)
@@ -182,6 +183,7 @@ StepParams step_params(const lbm_lattice *L) {
     p.tiles_per_xcd = (L->n_tiles + 7) / 8;
     p.tx_log2 = L->tx_log2;
     p.mask = L->d_mask;
+    p.cls = L->d_cls;
     p.uniform_tag = L->uniform_tag;
     p.has_force = (c.force[0] != 0.0 || c.force[1] != 0.0 || c.force[2] != 0.0) ? 1 : 0;
     p.has_mlp = L->has_mlp ? 1 : 0;
@@ -480,13 +482,20 @@ static lbm_status create_impl(const lbm_config *cfg, const uint8_t *tags_host, v
             L->d_mask = nullptr;
             return bail(set_err(LBM_ENOMEM, "hipMalloc of neighbour masks failed"));
         }
+        e = hipMalloc(&L->d_cls, (size_t)N);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            L->d_cls = nullptr;
+            return bail(set_err(LBM_ENOMEM, "hipMalloc of node classes failed"));
+        }
     }
     e = hipMemcpyAsync(L->d_tags, tags_host, (size_t)N, hipMemcpyHostToDevice, L->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(L->d_wall, cfg->wall_velocity, 16 * 3 * sizeof(double), hipMemcpyHostToDevice, L->stream);
     if (e == hipSuccess && L->tagged)
-        e = cfg->q == 19 ? launch_build_mask<19>(L->d_tags, cfg->nx, cfg->ny, cfg->nz, L->d_mask, L->stream)
-                         : launch_build_mask<27>(L->d_tags, cfg->nx, cfg->ny, cfg->nz, L->d_mask, L->stream);
+        e = cfg->q == 19
+                ? launch_build_mask<19>(L->d_tags, cfg->nx, cfg->ny, cfg->nz, L->d_mask, L->d_cls, L->stream)
+                : launch_build_mask<27>(L->d_tags, cfg->nx, cfg->ny, cfg->nz, L->d_mask, L->d_cls, L->stream);
     if (e == hipSuccess && L->tagged) e = launch_tile_classify(step_params(L), L->d_tile_tag, L->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
     if (e != hipSuccess) return bail(lbmd_fail_hip(nullptr, e, "tag upload"));
@@ -517,6 +526,7 @@ extern "C" void lbm_destroy(lbm_lattice *lat) {
     if (lat->d_stage1) (void)hipFree(lat->d_stage1);
     if (lat->d_tile_tag) (void)hipFree(lat->d_tile_tag);
     if (lat->d_mask) (void)hipFree(lat->d_mask);
+    if (lat->d_cls) (void)hipFree(lat->d_cls);
     if (lat->d_series) (void)hipFree(lat->d_series);
     lbmd_free_mlp(lat);
     delete lat;

@@ -60,6 +60,7 @@ struct StepParams {
     const uint8_t *tile_tag;  // per tile: the single fluid tag of the tile and its
                               // one-node halo, or 0 if its nodes read `mask`
     const uint32_t *mask;     // per-node neighbour mask (TAGGED variants)
+    const uint8_t *cls;       // per-node class: own fluid tag | 0x80 if next to a wall
     const double *wall_u;     // [16][3] moving-wall velocities (device)
     double *partials;         // [NRED][partial_stride] per-tile reduction partials
     long long stride;         // elements per population slot (padded plane)
@@ -106,7 +107,8 @@ enum GatherMode : int { G_POPS = 0, G_FIELDS = 1, G_CELLS = 2 };
 template <int Q, int P>
 hipError_t launch_step(const StepParams &p, int ms, bool tagged, int mode, int parity, hipStream_t s);
 template <int Q>
-hipError_t launch_build_mask(const uint8_t *tags, int nx, int ny, int nz, uint32_t *mask, hipStream_t s);
+hipError_t launch_build_mask(const uint8_t *tags, int nx, int ny, int nz, uint32_t *mask, uint8_t *cls,
+                             hipStream_t s);
 template <int Q, int P>
 hipError_t launch_init(const AuxParams &a, hipStream_t s);
 template <int Q, int P>

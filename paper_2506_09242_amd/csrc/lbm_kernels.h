@@ -222,53 +222,60 @@ __global__ __launch_bounds__(256) void k_collide_stream(StepParams p) {
     const int n = zo[1] + yo[1] + xo[1];
 
     // Node class.  Tiles whose one-node halo is a single fluid model (the
-    // interior of a walled domain) need nothing; other tiles read the node's
-    // precomputed neighbour mask (block-uniform branch).
+    // interior of a walled domain) need nothing; other tiles read one class
+    // byte per node, and only nodes next to a wall read their 32-bit mask.
+    const long long st = p.stride;
+    S *__restrict__ f = static_cast<S *>(p.pops);
     int tag = p.uniform_tag;
+    int cls = 0;
+    bool plain = true;
+    if constexpr (TAGGED) {
+        const int tile_tag = p.tile_tag[L];
+        plain = tile_tag != 0;
+        if (plain) tag = tile_tag;
+        else cls = p.cls[n];  // n is a valid node for inactive lanes too
+    }
+
+    // ---- pull the node's populations, first at the wall-free addresses (issued
+    // together with the class load; inactive lanes read node 0 harmlessly)
+    C h[Q];
+    sfor<Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        using Vi = V<Q, i>;
+        long long off;
+        if constexpr (PARITY == 0 || i == 0) {
+            off = (long long)i * st + n;
+        } else {
+            // direction i arrives from x - c_i (slot opp)
+            off = (long long)Vi::opp * st + (zo[1 - Vi::z] + yo[1 - Vi::y] + xo[1 - Vi::x]);
+        }
+        h[i] = (C)f[off];
+    });
+
     uint32_t wall = 0;   // bit i: node x + c_i is not fluid
     bool moving = false; // some neighbour is a moving wall
     if constexpr (TAGGED) {
-        const int tile_tag = p.tile_tag[L];
-        if (tile_tag != 0) {
-            tag = tile_tag;
-        } else {
-            const uint32_t m = active ? p.mask[n] : 0u;
-            wall = m & kMaskWalls;
-            moving = (m >> kMaskMovingBit) & 1u;
-            tag = (int)(m >> kMaskTagShift);
+        if (!plain) {
+            tag = cls & 0x7f;
+            if (cls & 0x80) {
+                const uint32_t m = p.mask[n];
+                wall = m & kMaskWalls;
+                moving = (m >> kMaskMovingBit) & 1u;
+                if constexpr (PARITY == 1) {
+                    // odd step: a direction whose upstream node x - c_i is a wall
+                    // comes back from the node's own slot i instead
+                    sfor<Q>([&](auto I) {
+                        constexpr int i = decltype(I)::value;
+                        using Vi = V<Q, i>;
+                        if constexpr (i > 0) {
+                            if ((wall >> Vi::opp) & 1u) h[i] = (C)f[(long long)i * st + n];
+                        }
+                    });
+                }
+            }
         }
     }
     const bool live = active && (!TAGGED || tag != 0);
-
-    const long long st = p.stride;
-    S *__restrict__ f = static_cast<S *>(p.pops);
-
-    // ---- pull the node's populations
-    C h[Q];
-    if (live) {
-        sfor<Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            using Vi = V<Q, i>;
-            long long off;
-            if constexpr (PARITY == 0 || i == 0) {
-                off = (long long)i * st + n;
-            } else {
-                // direction i arrives from x - c_i (slot opp), or from the node's
-                // own slot i when x - c_i is a wall
-                const int src = zo[1 - Vi::z] + yo[1 - Vi::y] + xo[1 - Vi::x];
-                const long long o_nb = (long long)Vi::opp * st + src;
-                if constexpr (TAGGED) {
-                    const bool wb = (wall >> Vi::opp) & 1u;
-                    off = wb ? (long long)i * st + n : o_nb;
-                } else {
-                    off = o_nb;
-                }
-            }
-            h[i] = (C)f[off];
-        });
-    } else {
-        sfor<Q>([&](auto I) { h[decltype(I)::value] = C(0); });
-    }
 
     double red[NRED];
     if constexpr (MODE != MODE_STEP) {
@@ -352,7 +359,8 @@ __global__ __launch_bounds__(256) void k_collide_stream(StepParams p) {
 // Neighbour mask of every node (see kMask*): wall bits, moving-wall flag and
 // the node's own fluid tag (0 for non-fluid nodes).
 template <int Q>
-__global__ __launch_bounds__(256) void k_build_mask(const uint8_t *tags, int nx, int ny, int nz, uint32_t *mask) {
+__global__ __launch_bounds__(256) void k_build_mask(const uint8_t *tags, int nx, int ny, int nz, uint32_t *mask,
+                                                    uint8_t *cls) {
     const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
     const long long N = (long long)nx * ny * nz;
     if (t >= N) return;
@@ -373,6 +381,7 @@ __global__ __launch_bounds__(256) void k_build_mask(const uint8_t *tags, int nx,
         });
     }
     mask[t] = m;
+    cls[t] = (uint8_t)((m >> kMaskTagShift) | ((m & kMaskWalls) ? 0x80u : 0u));
 }
 
 // ------------------------------------------------------------- helpers
@@ -515,9 +524,10 @@ hipError_t launch_step(const StepParams &p, int ms, bool tagged, int mode, int p
 }
 
 template <int Q>
-hipError_t launch_build_mask(const uint8_t *tags, int nx, int ny, int nz, uint32_t *mask, hipStream_t s) {
+hipError_t launch_build_mask(const uint8_t *tags, int nx, int ny, int nz, uint32_t *mask, uint8_t *cls,
+                             hipStream_t s) {
     const long long N = (long long)nx * ny * nz;
-    k_build_mask<Q><<<(unsigned)((N + 255) / 256), 256, 0, s>>>(tags, nx, ny, nz, mask);
+    k_build_mask<Q><<<(unsigned)((N + 255) / 256), 256, 0, s>>>(tags, nx, ny, nz, mask, cls);
     return hipGetLastError();
 }
 
