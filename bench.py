@@ -83,7 +83,10 @@ def alg_bytes_per_launch(tags, q, prec_bytes):
     return fluid * 2 * q * prec_bytes + tags.size, fluid
 
 
-def run_dtype(tags, kw, rho, u, prec, steps, warmup, every):
+def run_dtype(tags, kw, rho, u, prec, steps, warmup, every, chunk=2000, label=""):
+    """Time `steps` steps (reductions every `every`, fused) after `warmup`.  Long
+    runs go in chunks of about `chunk` steps (a multiple of `every`) with one
+    progress line each; the events bracket all chunks."""
     import torch
     from paper_2506_09242_amd import lbm
     stream = torch.cuda.current_stream()
@@ -95,9 +98,17 @@ def run_dtype(tags, kw, rho, u, prec, steps, warmup, every):
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
+    chunk = max(every, chunk // every * every)
     t0 = time.perf_counter()
     e0.record(stream)
-    series = L.step_reduce(steps, every)  # synchronizes at its end
+    series, done = [], 0
+    while done < steps:
+        n = min(chunk, steps - done)
+        part = L.step_reduce(n, every)  # synchronizes at its end
+        series.extend(part if not series else part[1:])
+        done += n
+        if steps > chunk:
+            print(f"# {label}: {done}/{steps} steps, {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -198,7 +209,7 @@ def main():
     results = {}
     for pn in prec_names:
         prec = lbm.PREC_NAMES[pn]
-        r = run_dtype(tags, kw, rho, u, prec, args.steps, args.warmup, args.every)
+        r = run_dtype(tags, kw, rho, u, prec, args.steps, args.warmup, args.every, label=pn)
         nbytes, nfluid = alg_bytes_per_launch(tags, kw["q"], lbm.PREC_BYTES[prec])
         launch_s = r["ms"] * 1e-3 / args.steps
         achieved = nbytes / launch_s / 1e9
@@ -244,7 +255,10 @@ def main():
             k_lu = nu * ux_mean / F
             derived[pn] = {"permeability_lu": k_lu, "permeability_mD": k_lu * (5.345e-6) ** 2 / 9.869233e-16,
                            "porosity": float(np.isin(tags, (1, 2, 3, 4)).mean()),
-                           "steps_total": args.warmup + args.steps}
+                           "steps_total": args.warmup + args.steps,
+                           "k_series_lu": [nu * m["velocity_sum"][0] / tags.size / F for m in r["series"][::20]]}
+        from paper_2506_09242_amd import inputs as _inp
+        derived["percolates_x"] = bool(_inp.percolates_x(tags))
 
     main_p = prec_names[0]
     m = results[main_p]

@@ -41,7 +41,8 @@ def dissipation(t, k):
     return -np.gradient(np.asarray(k), np.asarray(t))
 
 
-def run_tgv(n, tag, steps, every, prec=lbm.LBM_F32, cs=0.1, mlp=None, snapshots=(), factor=4, stream=None):
+def run_tgv(n, tag, steps, every, prec=lbm.LBM_F32, cs=0.1, mlp=None, snapshots=(), factor=4, stream=None,
+            log=None):
     """Run a D3Q27 Taylor-Green lattice; returns (t_steps, k, snapshots, seconds)."""
     import torch
     nu, tau, tc = tgv_setup(n)
@@ -76,6 +77,8 @@ def run_tgv(n, tag, steps, every, prec=lbm.LBM_F32, cs=0.1, mlp=None, snapshots=
                     ts.append(m["step"])
                     ks.append(m["kinetic_energy"])
             t = sp
+            if log is not None:
+                log(f"{n}^3 tag {tag}: step {t}/{steps}, {elapsed:.1f} s")
         if sp in marks:
             nc = (n // factor) ** 3
             feat = torch.empty((nc, 7), dtype=torch.float32, device="cuda")
@@ -116,7 +119,7 @@ def experiment(n_fine=512, factor=4, n_snap=16, n_samples=1_000_000, epochs=30, 
     snap_at = [int(round(s)) for s in np.linspace(0, steps_f, n_snap)]
     log(f"fine run {n_fine}^3, {steps_f} steps, snapshots at {snap_at[:3]}...")
     t_f, k_f, snaps, sec_f, bad_f = run_tgv(n_fine, inputs.TAG_SMAG, steps_f, every_fine, snapshots=snap_at,
-                                           factor=factor)
+                                           factor=factor, log=log)
     P, loss_log, sec_train, info = train_closure(snaps, n_samples=n_samples, epochs=epochs)
     del snaps
     log(f"trained on {info['samples']} of {info['pool']} samples, loss {loss_log[0]:.4g} -> {loss_log[-1]:.4g}")

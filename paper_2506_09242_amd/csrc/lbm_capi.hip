@@ -272,10 +272,11 @@ __global__ __launch_bounds__(256) void k_finalize2(const double *stage1, int nb,
     }
 }
 
-// One block per tile: load the tile's tags with a one-node halo (periodic)
-// and report the tag if every one of them is the same fluid tag, else 0.
+// One block per tile: the fluid tag if the tile and its one-node halo
+// (periodic) all carry it, else kTileExact when more than 1/8 of the tile's
+// own nodes are not fluid, else kTileSpeculative.
 __global__ __launch_bounds__(256) void k_tile_classify(StepParams p, uint8_t *out) {
-    __shared__ int s_first, s_same;
+    __shared__ int s_first, s_same, s_solid;
     const int L = blockIdx.x;
     const int txl = p.tx_log2;
     const int TX = 1 << txl, TY = 256 >> txl;
@@ -286,6 +287,7 @@ __global__ __launch_bounds__(256) void k_tile_classify(StepParams p, uint8_t *ou
     if (threadIdx.x == 0) {
         s_first = p.tags[((long long)z * p.ny + y0) * p.nx + x0];
         s_same = 1;
+        s_solid = 0;
     }
     __syncthreads();
     const int first = s_first;
@@ -297,8 +299,14 @@ __global__ __launch_bounds__(256) void k_tile_classify(StepParams p, uint8_t *ou
         if (p.tags[((long long)gz * p.ny + gy) * p.nx + gx] != first) same = false;
     }
     if (!same) s_same = 0;
+    // non-fluid nodes inside the tile (ragged lanes count as non-fluid)
+    const int lx = threadIdx.x & (TX - 1), ly = threadIdx.x >> txl;
+    const int x = x0 + lx, y = y0 + ly;
+    const bool fl = x < p.nx && y < p.ny && is_fluid_tag(p.tags[((long long)z * p.ny + y) * p.nx + x]);
+    if (!fl) atomicAdd(&s_solid, 1);
     __syncthreads();
-    if (threadIdx.x == 0) out[L] = s_same ? (uint8_t)first : (uint8_t)0;
+    if (threadIdx.x == 0)
+        out[L] = s_same ? (uint8_t)first : (uint8_t)(s_solid * 8 > 256 ? kTileExact : kTileSpeculative);
 }
 
 hipError_t launch_tile_classify(const StepParams &p, uint8_t *out, hipStream_t s) {

@@ -29,6 +29,11 @@ constexpr int kModelSets[] = {MS_BGK, MS_TRT, MS_BGK | MS_SMAG, MS_BGK | MS_SMAG
                               MS_BGK | MS_TRT | MS_SMAG | MS_MLP};
 constexpr int kNumModelSets = 5;
 
+// Tile classes beyond the plain fluid tags 1..4 (see k_collide_stream).
+constexpr int kTileSpecial = 0xc0;
+constexpr int kTileSpeculative = 0x40;  // few non-fluid nodes inside the tile
+constexpr int kTileExact = 0x80;        // more than 1/8 of the tile's nodes non-fluid
+
 // Kernel modes.
 enum StepMode : int {
     MODE_STEP = 0,        // collide + stream
@@ -57,8 +62,9 @@ struct MlpDev {
 struct StepParams {
     void *pops;               // population array, Q slots of `stride` elements
     const uint8_t *tags;      // device tags (TAGGED variants)
-    const uint8_t *tile_tag;  // per tile: the single fluid tag of the tile and its
-                              // one-node halo, or 0 if its nodes read `mask`
+    const uint8_t *tile_tag;  // per tile class: the fluid tag (1..4) when the tile and its
+                              // one-node halo are that one model, else kTileSpeculative
+                              // or kTileExact
     const uint32_t *mask;     // per-node neighbour mask (TAGGED variants)
     const uint8_t *cls;       // per-node class: own fluid tag | 0x80 if next to a wall
     const double *wall_u;     // [16][3] moving-wall velocities (device)

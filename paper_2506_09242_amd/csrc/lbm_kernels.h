@@ -221,58 +221,81 @@ __global__ __launch_bounds__(256) void k_collide_stream(StepParams p) {
     const int zo[3] = {(z == 0 ? nz - 1 : z - 1) * nxy, z * nxy, (z + 1 == nz ? 0 : z + 1) * nxy};
     const int n = zo[1] + yo[1] + xo[1];
 
-    // Node class.  Tiles whose one-node halo is a single fluid model (the
-    // interior of a walled domain) need nothing; other tiles read one class
-    // byte per node, and only nodes next to a wall read their 32-bit mask.
+    // Node class.  The tile class (block-uniform) picks one of three load paths:
+    //  - plain: the tile and its one-node halo are one fluid model (the
+    //    interior of a walled domain): no per-node data at all;
+    //  - speculative (few non-fluid nodes): one class byte per node is loaded
+    //    together with the populations at their wall-free addresses; nodes
+    //    next to a wall then read their 32-bit mask and re-load the few
+    //    directions that bounce back;
+    //  - exact (many non-fluid nodes, e.g. porous rock): class and mask first,
+    //    then loads for fluid nodes only, at wall-resolved addresses.
     const long long st = p.stride;
     S *__restrict__ f = static_cast<S *>(p.pops);
     int tag = p.uniform_tag;
-    int cls = 0;
-    bool plain = true;
-    if constexpr (TAGGED) {
-        const int tile_tag = p.tile_tag[L];
-        plain = tile_tag != 0;
-        if (plain) tag = tile_tag;
-        else cls = p.cls[n];  // n is a valid node for inactive lanes too
-    }
-
-    // ---- pull the node's populations, first at the wall-free addresses (issued
-    // together with the class load; inactive lanes read node 0 harmlessly)
-    C h[Q];
-    sfor<Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        using Vi = V<Q, i>;
-        long long off;
-        if constexpr (PARITY == 0 || i == 0) {
-            off = (long long)i * st + n;
-        } else {
-            // direction i arrives from x - c_i (slot opp)
-            off = (long long)Vi::opp * st + (zo[1 - Vi::z] + yo[1 - Vi::y] + xo[1 - Vi::x]);
-        }
-        h[i] = (C)f[off];
-    });
-
     uint32_t wall = 0;   // bit i: node x + c_i is not fluid
     bool moving = false; // some neighbour is a moving wall
-    if constexpr (TAGGED) {
-        if (!plain) {
-            tag = cls & 0x7f;
-            if (cls & 0x80) {
-                const uint32_t m = p.mask[n];
-                wall = m & kMaskWalls;
-                moving = (m >> kMaskMovingBit) & 1u;
-                if constexpr (PARITY == 1) {
-                    // odd step: a direction whose upstream node x - c_i is a wall
-                    // comes back from the node's own slot i instead
-                    sfor<Q>([&](auto I) {
-                        constexpr int i = decltype(I)::value;
-                        using Vi = V<Q, i>;
-                        if constexpr (i > 0) {
-                            if ((wall >> Vi::opp) & 1u) h[i] = (C)f[(long long)i * st + n];
-                        }
-                    });
-                }
+    C h[Q];
+    const int tile_class = TAGGED ? p.tile_tag[L] : 0;
+    auto load_free = [&]() {  // wall-free addresses; inactive lanes read node 0 harmlessly
+        sfor<Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            using Vi = V<Q, i>;
+            long long off;
+            if constexpr (PARITY == 0 || i == 0) {
+                off = (long long)i * st + n;
+            } else {
+                // direction i arrives from x - c_i (slot opp)
+                off = (long long)Vi::opp * st + (zo[1 - Vi::z] + yo[1 - Vi::y] + xo[1 - Vi::x]);
             }
+            h[i] = (C)f[off];
+        });
+    };
+    auto read_mask = [&]() {
+        const uint32_t m = p.mask[n];
+        wall = m & kMaskWalls;
+        moving = (m >> kMaskMovingBit) & 1u;
+    };
+    if (!TAGGED || (tile_class & kTileSpecial) == 0) {
+        if (TAGGED) tag = tile_class;
+        load_free();
+    } else if (tile_class == kTileSpeculative) {
+        const int cls = p.cls[n];  // n is a valid node for inactive lanes too
+        load_free();
+        tag = cls & 0x7f;
+        if (cls & 0x80) {
+            read_mask();
+            if constexpr (PARITY == 1) {
+                // odd step: a direction whose upstream node x - c_i is a wall
+                // comes back from the node's own slot i instead
+                sfor<Q>([&](auto I) {
+                    constexpr int i = decltype(I)::value;
+                    using Vi = V<Q, i>;
+                    if constexpr (i > 0) {
+                        if ((wall >> Vi::opp) & 1u) h[i] = (C)f[(long long)i * st + n];
+                    }
+                });
+            }
+        }
+    } else {
+        const int cls = active ? p.cls[n] : 0;
+        tag = cls & 0x7f;
+        if (cls & 0x80) read_mask();
+        sfor<Q>([&](auto I) { h[decltype(I)::value] = C(0); });
+        if (tag != 0) {
+            sfor<Q>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                using Vi = V<Q, i>;
+                long long off;
+                if constexpr (PARITY == 0 || i == 0) {
+                    off = (long long)i * st + n;
+                } else {
+                    const long long o_nb =
+                        (long long)Vi::opp * st + (zo[1 - Vi::z] + yo[1 - Vi::y] + xo[1 - Vi::x]);
+                    off = ((wall >> Vi::opp) & 1u) ? (long long)i * st + n : o_nb;
+                }
+                h[i] = (C)f[off];
+            });
         }
     }
     const bool live = active && (!TAGGED || tag != 0);
