@@ -47,7 +47,6 @@ struct lbm_lattice {
     double *d_stage1 = nullptr;     // [NRED][kFinalizeBlocks]
     uint8_t *d_tile_tag = nullptr;  // [max_tiles] tile classification of the current tiling
     uint32_t *d_mask = nullptr;     // [N] neighbour masks (tagged lattices)
-    uint8_t *d_cls = nullptr;       // [N] node classes (tagged lattices)
     double *d_series = nullptr;     // [series_cap][NRED]
     long long series_cap = 0;
     void *d_mlp = nullptr;          // packed closure block (lbm_mlp.hip)
@@ -183,7 +182,6 @@ StepParams step_params(const lbm_lattice *L) {
     p.tiles_per_xcd = (L->n_tiles + 7) / 8;
     p.tx_log2 = L->tx_log2;
     p.mask = L->d_mask;
-    p.cls = L->d_cls;
     p.uniform_tag = L->uniform_tag;
     p.has_force = (c.force[0] != 0.0 || c.force[1] != 0.0 || c.force[2] != 0.0) ? 1 : 0;
     p.has_mlp = L->has_mlp ? 1 : 0;
@@ -272,11 +270,10 @@ __global__ __launch_bounds__(256) void k_finalize2(const double *stage1, int nb,
     }
 }
 
-// One block per tile: the fluid tag if the tile and its one-node halo
-// (periodic) all carry it, else kTileExact when more than 1/8 of the tile's
-// own nodes are not fluid, else kTileSpeculative.
+// One block per tile: load the tile's tags with a one-node halo (periodic)
+// and report the tag if every one of them is the same fluid tag, else 0.
 __global__ __launch_bounds__(256) void k_tile_classify(StepParams p, uint8_t *out) {
-    __shared__ int s_first, s_same, s_solid;
+    __shared__ int s_first, s_same;
     const int L = blockIdx.x;
     const int txl = p.tx_log2;
     const int TX = 1 << txl, TY = 256 >> txl;
@@ -287,7 +284,6 @@ __global__ __launch_bounds__(256) void k_tile_classify(StepParams p, uint8_t *ou
     if (threadIdx.x == 0) {
         s_first = p.tags[((long long)z * p.ny + y0) * p.nx + x0];
         s_same = 1;
-        s_solid = 0;
     }
     __syncthreads();
     const int first = s_first;
@@ -299,14 +295,8 @@ __global__ __launch_bounds__(256) void k_tile_classify(StepParams p, uint8_t *ou
         if (p.tags[((long long)gz * p.ny + gy) * p.nx + gx] != first) same = false;
     }
     if (!same) s_same = 0;
-    // non-fluid nodes inside the tile (ragged lanes count as non-fluid)
-    const int lx = threadIdx.x & (TX - 1), ly = threadIdx.x >> txl;
-    const int x = x0 + lx, y = y0 + ly;
-    const bool fl = x < p.nx && y < p.ny && is_fluid_tag(p.tags[((long long)z * p.ny + y) * p.nx + x]);
-    if (!fl) atomicAdd(&s_solid, 1);
     __syncthreads();
-    if (threadIdx.x == 0)
-        out[L] = s_same ? (uint8_t)first : (uint8_t)(s_solid * 8 > 256 ? kTileExact : kTileSpeculative);
+    if (threadIdx.x == 0) out[L] = s_same ? (uint8_t)first : (uint8_t)0;
 }
 
 hipError_t launch_tile_classify(const StepParams &p, uint8_t *out, hipStream_t s) {
@@ -490,20 +480,13 @@ static lbm_status create_impl(const lbm_config *cfg, const uint8_t *tags_host, v
             L->d_mask = nullptr;
             return bail(set_err(LBM_ENOMEM, "hipMalloc of neighbour masks failed"));
         }
-        e = hipMalloc(&L->d_cls, (size_t)N);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            L->d_cls = nullptr;
-            return bail(set_err(LBM_ENOMEM, "hipMalloc of node classes failed"));
-        }
     }
     e = hipMemcpyAsync(L->d_tags, tags_host, (size_t)N, hipMemcpyHostToDevice, L->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(L->d_wall, cfg->wall_velocity, 16 * 3 * sizeof(double), hipMemcpyHostToDevice, L->stream);
     if (e == hipSuccess && L->tagged)
-        e = cfg->q == 19
-                ? launch_build_mask<19>(L->d_tags, cfg->nx, cfg->ny, cfg->nz, L->d_mask, L->d_cls, L->stream)
-                : launch_build_mask<27>(L->d_tags, cfg->nx, cfg->ny, cfg->nz, L->d_mask, L->d_cls, L->stream);
+        e = cfg->q == 19 ? launch_build_mask<19>(L->d_tags, cfg->nx, cfg->ny, cfg->nz, L->d_mask, L->stream)
+                         : launch_build_mask<27>(L->d_tags, cfg->nx, cfg->ny, cfg->nz, L->d_mask, L->stream);
     if (e == hipSuccess && L->tagged) e = launch_tile_classify(step_params(L), L->d_tile_tag, L->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
     if (e != hipSuccess) return bail(lbmd_fail_hip(nullptr, e, "tag upload"));
@@ -534,7 +517,6 @@ extern "C" void lbm_destroy(lbm_lattice *lat) {
     if (lat->d_stage1) (void)hipFree(lat->d_stage1);
     if (lat->d_tile_tag) (void)hipFree(lat->d_tile_tag);
     if (lat->d_mask) (void)hipFree(lat->d_mask);
-    if (lat->d_cls) (void)hipFree(lat->d_cls);
     if (lat->d_series) (void)hipFree(lat->d_series);
     lbmd_free_mlp(lat);
     delete lat;

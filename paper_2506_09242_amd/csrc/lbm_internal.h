@@ -29,11 +29,6 @@ constexpr int kModelSets[] = {MS_BGK, MS_TRT, MS_BGK | MS_SMAG, MS_BGK | MS_SMAG
                               MS_BGK | MS_TRT | MS_SMAG | MS_MLP};
 constexpr int kNumModelSets = 5;
 
-// Tile classes beyond the plain fluid tags 1..4 (see k_collide_stream).
-constexpr int kTileSpecial = 0xc0;
-constexpr int kTileSpeculative = 0x40;  // few non-fluid nodes inside the tile
-constexpr int kTileExact = 0x80;        // more than 1/8 of the tile's nodes non-fluid
-
 // Kernel modes.
 enum StepMode : int {
     MODE_STEP = 0,        // collide + stream
@@ -62,11 +57,9 @@ struct MlpDev {
 struct StepParams {
     void *pops;               // population array, Q slots of `stride` elements
     const uint8_t *tags;      // device tags (TAGGED variants)
-    const uint8_t *tile_tag;  // per tile class: the fluid tag (1..4) when the tile and its
-                              // one-node halo are that one model, else kTileSpeculative
-                              // or kTileExact
+    const uint8_t *tile_tag;  // per tile: the fluid tag (1..4) when the tile and its
+                              // one-node halo are that one model, else 0
     const uint32_t *mask;     // per-node neighbour mask (TAGGED variants)
-    const uint8_t *cls;       // per-node class: own fluid tag | 0x80 if next to a wall
     const double *wall_u;     // [16][3] moving-wall velocities (device)
     double *partials;         // [NRED][partial_stride] per-tile reduction partials
     long long stride;         // elements per population slot (padded plane)
@@ -113,8 +106,7 @@ enum GatherMode : int { G_POPS = 0, G_FIELDS = 1, G_CELLS = 2 };
 template <int Q, int P>
 hipError_t launch_step(const StepParams &p, int ms, bool tagged, int mode, int parity, hipStream_t s);
 template <int Q>
-hipError_t launch_build_mask(const uint8_t *tags, int nx, int ny, int nz, uint32_t *mask, uint8_t *cls,
-                             hipStream_t s);
+hipError_t launch_build_mask(const uint8_t *tags, int nx, int ny, int nz, uint32_t *mask, hipStream_t s);
 template <int Q, int P>
 hipError_t launch_init(const AuxParams &a, hipStream_t s);
 template <int Q, int P>

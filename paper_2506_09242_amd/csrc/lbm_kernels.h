@@ -221,23 +221,33 @@ __global__ __launch_bounds__(256) void k_collide_stream(StepParams p) {
     const int zo[3] = {(z == 0 ? nz - 1 : z - 1) * nxy, z * nxy, (z + 1 == nz ? 0 : z + 1) * nxy};
     const int n = zo[1] + yo[1] + xo[1];
 
-    // Node class.  The tile class (block-uniform) picks one of three load paths:
-    //  - plain: the tile and its one-node halo are one fluid model (the
-    //    interior of a walled domain): no per-node data at all;
-    //  - speculative (few non-fluid nodes): one class byte per node is loaded
-    //    together with the populations at their wall-free addresses; nodes
-    //    next to a wall then read their 32-bit mask and re-load the few
-    //    directions that bounce back;
-    //  - exact (many non-fluid nodes, e.g. porous rock): class and mask first,
-    //    then loads for fluid nodes only, at wall-resolved addresses.
+    // Node class.  Tiles whose one-node halo is a single fluid model (the
+    // interior of a walled domain) need nothing; the other tiles read each
+    // node's precomputed neighbour mask (block-uniform branch).
     const long long st = p.stride;
     S *__restrict__ f = static_cast<S *>(p.pops);
     int tag = p.uniform_tag;
     uint32_t wall = 0;   // bit i: node x + c_i is not fluid
     bool moving = false; // some neighbour is a moving wall
+    if constexpr (TAGGED) {
+        const int tile_tag = p.tile_tag[L];
+        if (tile_tag != 0) {
+            tag = tile_tag;
+        } else {
+            const uint32_t m = active ? p.mask[n] : 0u;
+            wall = m & kMaskWalls;
+            moving = (m >> kMaskMovingBit) & 1u;
+            tag = (int)(m >> kMaskTagShift);
+        }
+    }
+    const bool live = active && (!TAGGED || tag != 0);
+
+    // ---- pull the node's populations.  The registers are zeroed first and the
+    // loads sit in a branch with no else: a divergent else that overwrote
+    // registers with loads in flight would force a wait on those loads.
     C h[Q];
-    const int tile_class = TAGGED ? p.tile_tag[L] : 0;
-    auto load_free = [&]() {  // wall-free addresses; inactive lanes read node 0 harmlessly
+    sfor<Q>([&](auto I) { h[decltype(I)::value] = C(0); });
+    if (live) {
         sfor<Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
             using Vi = V<Q, i>;
@@ -245,60 +255,18 @@ __global__ __launch_bounds__(256) void k_collide_stream(StepParams p) {
             if constexpr (PARITY == 0 || i == 0) {
                 off = (long long)i * st + n;
             } else {
-                // direction i arrives from x - c_i (slot opp)
-                off = (long long)Vi::opp * st + (zo[1 - Vi::z] + yo[1 - Vi::y] + xo[1 - Vi::x]);
+                // direction i arrives from x - c_i (slot opp), or from the node's
+                // own slot i when x - c_i is a wall
+                const long long o_nb = (long long)Vi::opp * st + (zo[1 - Vi::z] + yo[1 - Vi::y] + xo[1 - Vi::x]);
+                if constexpr (TAGGED) {
+                    off = ((wall >> Vi::opp) & 1u) ? (long long)i * st + n : o_nb;
+                } else {
+                    off = o_nb;
+                }
             }
             h[i] = (C)f[off];
         });
-    };
-    auto read_mask = [&]() {
-        const uint32_t m = p.mask[n];
-        wall = m & kMaskWalls;
-        moving = (m >> kMaskMovingBit) & 1u;
-    };
-    if (!TAGGED || (tile_class & kTileSpecial) == 0) {
-        if (TAGGED) tag = tile_class;
-        load_free();
-    } else if (tile_class == kTileSpeculative) {
-        const int cls = p.cls[n];  // n is a valid node for inactive lanes too
-        load_free();
-        tag = cls & 0x7f;
-        if (cls & 0x80) {
-            read_mask();
-            if constexpr (PARITY == 1) {
-                // odd step: a direction whose upstream node x - c_i is a wall
-                // comes back from the node's own slot i instead
-                sfor<Q>([&](auto I) {
-                    constexpr int i = decltype(I)::value;
-                    using Vi = V<Q, i>;
-                    if constexpr (i > 0) {
-                        if ((wall >> Vi::opp) & 1u) h[i] = (C)f[(long long)i * st + n];
-                    }
-                });
-            }
-        }
-    } else {
-        const int cls = active ? p.cls[n] : 0;
-        tag = cls & 0x7f;
-        if (cls & 0x80) read_mask();
-        sfor<Q>([&](auto I) { h[decltype(I)::value] = C(0); });
-        if (tag != 0) {
-            sfor<Q>([&](auto I) {
-                constexpr int i = decltype(I)::value;
-                using Vi = V<Q, i>;
-                long long off;
-                if constexpr (PARITY == 0 || i == 0) {
-                    off = (long long)i * st + n;
-                } else {
-                    const long long o_nb =
-                        (long long)Vi::opp * st + (zo[1 - Vi::z] + yo[1 - Vi::y] + xo[1 - Vi::x]);
-                    off = ((wall >> Vi::opp) & 1u) ? (long long)i * st + n : o_nb;
-                }
-                h[i] = (C)f[off];
-            });
-        }
     }
-    const bool live = active && (!TAGGED || tag != 0);
 
     double red[NRED];
     if constexpr (MODE != MODE_STEP) {
@@ -349,8 +317,7 @@ __global__ __launch_bounds__(256) void k_collide_stream(StepParams p) {
                 } else {
                     // odd step: h*_i goes to slot i of x + c_i, or back to slot
                     // opp(i) of the node itself when x + c_i is a wall
-                    const int dst = zo[1 + Vi::z] + yo[1 + Vi::y] + xo[1 + Vi::x];
-                    off = (long long)i * st + dst;
+                    off = (long long)i * st + (zo[1 + Vi::z] + yo[1 + Vi::y] + xo[1 + Vi::x]);
                     if constexpr (TAGGED) {
                         if ((wall >> i) & 1u) off = (long long)Vi::opp * st + n;
                     }
@@ -382,8 +349,7 @@ __global__ __launch_bounds__(256) void k_collide_stream(StepParams p) {
 // Neighbour mask of every node (see kMask*): wall bits, moving-wall flag and
 // the node's own fluid tag (0 for non-fluid nodes).
 template <int Q>
-__global__ __launch_bounds__(256) void k_build_mask(const uint8_t *tags, int nx, int ny, int nz, uint32_t *mask,
-                                                    uint8_t *cls) {
+__global__ __launch_bounds__(256) void k_build_mask(const uint8_t *tags, int nx, int ny, int nz, uint32_t *mask) {
     const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
     const long long N = (long long)nx * ny * nz;
     if (t >= N) return;
@@ -404,7 +370,6 @@ __global__ __launch_bounds__(256) void k_build_mask(const uint8_t *tags, int nx,
         });
     }
     mask[t] = m;
-    cls[t] = (uint8_t)((m >> kMaskTagShift) | ((m & kMaskWalls) ? 0x80u : 0u));
 }
 
 // ------------------------------------------------------------- helpers
@@ -547,10 +512,9 @@ hipError_t launch_step(const StepParams &p, int ms, bool tagged, int mode, int p
 }
 
 template <int Q>
-hipError_t launch_build_mask(const uint8_t *tags, int nx, int ny, int nz, uint32_t *mask, uint8_t *cls,
-                             hipStream_t s) {
+hipError_t launch_build_mask(const uint8_t *tags, int nx, int ny, int nz, uint32_t *mask, hipStream_t s) {
     const long long N = (long long)nx * ny * nz;
-    k_build_mask<Q><<<(unsigned)((N + 255) / 256), 256, 0, s>>>(tags, nx, ny, nz, mask, cls);
+    k_build_mask<Q><<<(unsigned)((N + 255) / 256), 256, 0, s>>>(tags, nx, ny, nz, mask);
     return hipGetLastError();
 }
 

@@ -68,7 +68,8 @@ def test_aa_maps_are_race_free_and_consistent(q, shape, seed):
 def _aa_free_stream(q, shape, fluid, c, opp, f_nat, steps):
     """Apply `steps` AA steps with identity collision to natural-layout values and
     return the natural state (gathering after an odd step)."""
-    a = f_nat.copy()  # slot array a[i][z][y][x]
+    a = f_nat.copy()  # slot array a[i][z][y][x]; non-fluid nodes hold garbage
+    a[:, ~fluid] = np.nan
     for s in range(steps):
         parity = s % 2
         new = a.copy()
