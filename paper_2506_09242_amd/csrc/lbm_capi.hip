@@ -45,7 +45,7 @@ struct lbm_lattice {
     double *d_partials = nullptr;   // [NRED][max_tiles]
     long long max_tiles = 0;
     double *d_stage1 = nullptr;     // [NRED][kFinalizeBlocks]
-    uint8_t *d_tile_tag = nullptr;  // [max_tiles] tile classification of the current tiling
+    int *d_tile_tag = nullptr;      // [max_tiles] tile classification of the current tiling
     uint32_t *d_mask = nullptr;     // [N] neighbour masks (tagged lattices)
     double *d_series = nullptr;     // [series_cap][NRED]
     long long series_cap = 0;
@@ -272,7 +272,7 @@ __global__ __launch_bounds__(256) void k_finalize2(const double *stage1, int nb,
 
 // One block per tile: load the tile's tags with a one-node halo (periodic)
 // and report the tag if every one of them is the same fluid tag, else 0.
-__global__ __launch_bounds__(256) void k_tile_classify(StepParams p, uint8_t *out) {
+__global__ __launch_bounds__(256) void k_tile_classify(StepParams p, int *out) {
     __shared__ int s_first, s_same;
     const int L = blockIdx.x;
     const int txl = p.tx_log2;
@@ -296,10 +296,10 @@ __global__ __launch_bounds__(256) void k_tile_classify(StepParams p, uint8_t *ou
     }
     if (!same) s_same = 0;
     __syncthreads();
-    if (threadIdx.x == 0) out[L] = s_same ? (uint8_t)first : (uint8_t)0;
+    if (threadIdx.x == 0) out[L] = s_same ? first : 0;
 }
 
-hipError_t launch_tile_classify(const StepParams &p, uint8_t *out, hipStream_t s) {
+hipError_t launch_tile_classify(const StepParams &p, int *out, hipStream_t s) {
     k_tile_classify<<<p.n_tiles, 256, 0, s>>>(p, out);
     return hipGetLastError();
 }
@@ -467,7 +467,7 @@ static lbm_status create_impl(const lbm_config *cfg, const uint8_t *tags_host, v
         L->d_stage1 = nullptr;
         return bail(set_err(LBM_ENOMEM, "hipMalloc of reduction stage buffer failed"));
     }
-    e = hipMalloc(&L->d_tile_tag, (size_t)max_tiles);
+    e = hipMalloc(&L->d_tile_tag, (size_t)max_tiles * sizeof(int));
     if (e != hipSuccess) {
         (void)hipGetLastError();
         L->d_tile_tag = nullptr;

@@ -230,7 +230,9 @@ __global__ __launch_bounds__(256) void k_collide_stream(StepParams p) {
     uint32_t wall = 0;   // bit i: node x + c_i is not fluid
     bool moving = false; // some neighbour is a moving wall
     if constexpr (TAGGED) {
-        const int tile_tag = p.tile_tag[L];
+        // block-uniform entry read through the constant address space (scalar load)
+        typedef const __attribute__((address_space(4))) int const_int;
+        const int tile_tag = ((const_int *)p.tile_tag)[L];
         if (tile_tag != 0) {
             tag = tile_tag;
         } else {
