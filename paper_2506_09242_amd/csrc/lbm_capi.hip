@@ -117,6 +117,23 @@ long long slot_stride(long long ncell) { return (ncell + 127) / 128 * 128 + 128;
 
 bool known_tag(int t) { return (t >= 0 && t <= 4) || (t >= 16 && t <= 31); }
 
+// Storage sectors of 64 bytes hold 8 (FP64), 16 (FP32) or 32 (FP16) nodes.
+int sector_log2(int prec) { return prec == LBM_F64 ? 3 : (prec == LBM_F32 ? 4 : 5); }
+
+// Non-fluid nodes that share a storage sector with a fluid node (the step
+// kernel's filler nodes).
+long long count_fillers(const uint8_t *tags, long long N, int sector_log2) {
+    const long long g = 1ll << sector_log2;
+    long long count = 0;
+    for (long long a = 0; a < N; a += g) {
+        const long long b = a + g < N ? a + g : N;
+        long long fl = 0;
+        for (long long k = a; k < b; ++k) fl += (tags[k] >= 1 && tags[k] <= 4);
+        if (fl) count += (b - a) - fl;
+    }
+    return count;
+}
+
 lbm_status validate(const lbm_config *c) {
     if (!c) return set_err(LBM_EINVAL, "null config");
     if (c->nx < 1 || c->ny < 1 || c->nz < 1)
@@ -390,6 +407,11 @@ static lbm_status create_impl(const lbm_config *cfg, const uint8_t *tags_host, v
             only = t;
         }
     const bool tagged = !(nf == N && n_models == 1);
+    // Odd-step filler stores pay off where filler nodes are few (walls of a
+    // mostly fluid domain); in solid-rich media (porous rock) they add more
+    // scattered partial writes than they complete, so there only the even
+    // step fills.
+    const bool odd_fill = tagged && count_fillers(tags_host, N, sector_log2(cfg->prec)) * 16 <= nf;
 
     const size_t need_bytes = lbm_population_bytes(cfg);
     if (pops_dev) {
@@ -485,8 +507,10 @@ static lbm_status create_impl(const lbm_config *cfg, const uint8_t *tags_host, v
     if (e == hipSuccess)
         e = hipMemcpyAsync(L->d_wall, cfg->wall_velocity, 16 * 3 * sizeof(double), hipMemcpyHostToDevice, L->stream);
     if (e == hipSuccess && L->tagged)
-        e = cfg->q == 19 ? launch_build_mask<19>(L->d_tags, cfg->nx, cfg->ny, cfg->nz, L->d_mask, L->stream)
-                         : launch_build_mask<27>(L->d_tags, cfg->nx, cfg->ny, cfg->nz, L->d_mask, L->stream);
+        e = cfg->q == 19 ? launch_build_mask<19>(L->d_tags, cfg->nx, cfg->ny, cfg->nz, sector_log2(cfg->prec),
+                                                 odd_fill, L->d_mask, L->stream)
+                         : launch_build_mask<27>(L->d_tags, cfg->nx, cfg->ny, cfg->nz, sector_log2(cfg->prec),
+                                                 odd_fill, L->d_mask, L->stream);
     if (e == hipSuccess && L->tagged) e = launch_tile_classify(step_params(L), L->d_tile_tag, L->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
     if (e != hipSuccess) return bail(lbmd_fail_hip(nullptr, e, "tag upload"));

@@ -107,7 +107,10 @@ enum GatherMode : int { G_POPS = 0, G_FIELDS = 1, G_CELLS = 2 };
 template <int Q, int P>
 hipError_t launch_step(const StepParams &p, int ms, bool tagged, int mode, int parity, hipStream_t s);
 template <int Q>
-hipError_t launch_build_mask(const uint8_t *tags, int nx, int ny, int nz, uint32_t *mask, hipStream_t s);
+// sector_log2: log2 of the nodes per 64-byte storage sector in the lattice's
+// precision; odd_fill: also mark the odd-step filler targets.
+hipError_t launch_build_mask(const uint8_t *tags, int nx, int ny, int nz, int sector_log2, int odd_fill,
+                             uint32_t *mask, hipStream_t s);
 template <int Q, int P>
 hipError_t launch_init(const AuxParams &a, hipStream_t s);
 template <int Q, int P>

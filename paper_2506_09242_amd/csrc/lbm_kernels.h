@@ -40,9 +40,11 @@
 
 namespace lbmd {
 
-// Per-node neighbour mask layout: bits 0..26 wall bits (bit i set when node
-// x + c_i is not fluid), bit 27 set when a neighbour is a moving wall, bits
-// 28..31 the node's own fluid tag (0 for a non-fluid node).
+// Per-node neighbour mask layout.  Fluid node: bits 1..26 wall bits (bit i
+// set when node x + c_i is not fluid), bit 27 set when a neighbour is a moving
+// wall, bits 28..31 the node's own fluid tag.  Non-fluid node (tag bits 0):
+// zero, or a filler (see the step kernel) with bit 0 set and bit i set when
+// node x + (0, c_iy, c_iz) is not fluid.
 constexpr uint32_t kMaskWalls = (1u << 27) - 1u;
 constexpr int kMaskMovingBit = 27;
 constexpr int kMaskTagShift = 28;
@@ -243,6 +245,14 @@ __global__ __launch_bounds__(256) void k_collide_stream(StepParams p) {
         }
     }
     const bool live = active && (!TAGGED || tag != 0);
+    // Filler stores.  A non-fluid node that shares a 64-byte storage sector with
+    // fluid nodes stores into slots no fluid node reads or writes, so that the
+    // sectors the step writes are written whole instead of partially (partial
+    // sectors cost the memory a read-modify-write): in the even step its own
+    // slots; in the odd step slot i of node x + (0, c_iy, c_iz) when that node
+    // is not fluid (the row the wave's other lanes write for direction i).
+    // Its loaded values are zero and its stored values are never read.
+    const bool filler = TAGGED && active && tag == 0 && (wall & 1u);
 
     // ---- pull the node's populations.  The registers are zeroed first and the
     // loads sit in a branch with no else: a divergent else that overwrote
@@ -306,11 +316,12 @@ __global__ __launch_bounds__(256) void k_collide_stream(StepParams p) {
         }
 
         // ---- push
-        if (live) {
+        if (live || filler) {
             sfor<Q>([&](auto I) {
                 constexpr int i = decltype(I)::value;
                 using Vi = V<Q, i>;
                 long long off;
+                bool ok = true;
                 if constexpr (i == 0) {
                     off = n;
                 } else if constexpr (PARITY == 0) {
@@ -321,10 +332,13 @@ __global__ __launch_bounds__(256) void k_collide_stream(StepParams p) {
                     // opp(i) of the node itself when x + c_i is a wall
                     off = (long long)i * st + (zo[1 + Vi::z] + yo[1 + Vi::y] + xo[1 + Vi::x]);
                     if constexpr (TAGGED) {
-                        if ((wall >> i) & 1u) off = (long long)Vi::opp * st + n;
+                        const bool wi = (wall >> i) & 1u;
+                        if (wi) off = live ? (long long)Vi::opp * st + n
+                                           : (long long)i * st + (zo[1 + Vi::z] + yo[1 + Vi::y] + xo[1]);
+                        ok = live || wi;
                     }
                 }
-                f[off] = (S)hs[i];
+                if (ok) f[off] = (S)hs[i];
             });
         }
     }
@@ -351,11 +365,13 @@ __global__ __launch_bounds__(256) void k_collide_stream(StepParams p) {
 // Neighbour mask of every node (see kMask*): wall bits, moving-wall flag and
 // the node's own fluid tag (0 for non-fluid nodes).
 template <int Q>
-__global__ __launch_bounds__(256) void k_build_mask(const uint8_t *tags, int nx, int ny, int nz, uint32_t *mask) {
+__global__ __launch_bounds__(256) void k_build_mask(const uint8_t *tags, int nx, int ny, int nz, int sector_log2,
+                                                    int odd_fill, uint32_t *mask) {
     const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
     const long long N = (long long)nx * ny * nz;
     if (t >= N) return;
     const int x = (int)(t % nx), y = (int)((t / nx) % ny), z = (int)(t / ((long long)nx * ny));
+    auto fluid_at = [&](int gx, int gy, int gz) { return is_fluid_tag(tags[((long long)gz * ny + gy) * nx + gx]); };
     const int own = tags[t];
     uint32_t m = 0;
     if (is_fluid_tag(own)) {
@@ -370,6 +386,24 @@ __global__ __launch_bounds__(256) void k_build_mask(const uint8_t *tags, int nx,
                 if (tn >= LBM_TAG_WALL0) m |= 1u << kMaskMovingBit;
             }
         });
+    } else {
+        // filler: a non-fluid node in a storage sector that also holds fluid nodes
+        const long long g = 1ll << sector_log2;
+        const long long a = t & ~(g - 1), b = a + g < N ? a + g : N;
+        bool any = false;
+        for (long long k = a; k < b; ++k) any |= is_fluid_tag(tags[k]);
+        if (any) {
+            m = 1u;
+            if (odd_fill) {
+                sfor<Q>([&](auto I) {
+                    constexpr int i = decltype(I)::value;
+                    if constexpr (i > 0) {
+                        using Vi = V<Q, i>;
+                        if (!fluid_at(x, wrap_idx(y + Vi::y, ny), wrap_idx(z + Vi::z, nz))) m |= 1u << i;
+                    }
+                });
+            }
+        }
     }
     mask[t] = m;
 }
@@ -514,9 +548,10 @@ hipError_t launch_step(const StepParams &p, int ms, bool tagged, int mode, int p
 }
 
 template <int Q>
-hipError_t launch_build_mask(const uint8_t *tags, int nx, int ny, int nz, uint32_t *mask, hipStream_t s) {
+hipError_t launch_build_mask(const uint8_t *tags, int nx, int ny, int nz, int sector_log2, int odd_fill,
+                             uint32_t *mask, hipStream_t s) {
     const long long N = (long long)nx * ny * nz;
-    k_build_mask<Q><<<(unsigned)((N + 255) / 256), 256, 0, s>>>(tags, nx, ny, nz, mask);
+    k_build_mask<Q><<<(unsigned)((N + 255) / 256), 256, 0, s>>>(tags, nx, ny, nz, sector_log2, odd_fill, mask);
     return hipGetLastError();
 }
 

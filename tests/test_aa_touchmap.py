@@ -118,3 +118,73 @@ def test_aa_free_streaming_matches_push(q, steps):
     o.run(steps)
     aa = _aa_free_stream(q, shape, fluid, c, opp, f0, steps)
     assert np.array_equal(aa[:, fluid], o.f[:, fluid])
+
+
+def _filler_writes(q, shape, fluid, c, opp, parity, sector, odd_fill):
+    """(node, slot) targets of the step kernel's filler stores: a non-fluid node
+    whose storage sector (`sector` consecutive node indices) holds a fluid node
+    writes its own slots in the even step, and in the odd step slot 0 of itself
+    and slot i of node x + (0, c_iy, c_iz) where that node is not fluid."""
+    nz, ny, nx = shape
+    flat = fluid.reshape(-1)
+    out = []
+    for n in range(flat.size):
+        if flat[n]:
+            continue
+        a = n - n % sector
+        if not flat[a:a + sector].any():
+            continue
+        x = (n // (nx * ny), (n // nx) % ny, n % nx)
+        for i in range(q):
+            if parity == 0:
+                out.append((x, opp[i]))
+            elif i == 0:
+                out.append((x, 0))
+            elif odd_fill:
+                t = ((x[0] + c[i][2]) % nz, (x[1] + c[i][1]) % ny, x[2])
+                if not fluid[t]:
+                    out.append((t, i))
+    return out
+
+
+@pytest.mark.parametrize("q", [19, 27])
+@pytest.mark.parametrize("sector", [2, 4, 8])
+@pytest.mark.parametrize("shape,seed", [((3, 4, 5), 1), ((2, 3, 7), 2), ((4, 5, 6), 5)])
+def test_filler_stores_touch_only_dead_slots(q, sector, shape, seed):
+    tags, fluid, c, opp = _setup(q, shape, seed)
+    for parity in (0, 1):
+        r, w = _maps(q, shape, fluid, c, opp, parity)
+        live = set(r) | set(w)
+        for odd_fill in (False, True):
+            fw = _filler_writes(q, shape, fluid, c, opp, parity, sector, odd_fill)
+            # never a fluid node's slot, and no slot written twice by fillers
+            assert all(not fluid[x] for x, _ in fw)
+            assert not (set(fw) & live)
+            assert len(set(fw)) == len(fw)
+    # even step: every slot of every sector that holds a fluid node is written
+    nz, ny, nx = shape
+    _, w0 = _maps(q, shape, fluid, c, opp, 0)
+    written = set(w0) | set(_filler_writes(q, shape, fluid, c, opp, 0, sector, True))
+    flat = fluid.reshape(-1)
+    for a in range(0, flat.size, sector):
+        if flat[a:a + sector].any():
+            for n in range(a, min(a + sector, flat.size)):
+                x = (n // (nx * ny), (n // nx) % ny, n % nx)
+                assert all((x, i) in written for i in range(q))
+
+
+def test_filler_completes_rows_next_to_x_walls():
+    """A box with walls on the x faces: with odd-step fillers every sector of
+    every row that holds fluid is written whole in both steps."""
+    q, shape, sector = 19, (4, 4, 12), 4
+    nz, ny, nx = shape
+    fluid = np.ones(shape, bool)
+    fluid[:, :, 0] = fluid[:, :, -1] = False
+    c, w, opp = oracle.tables(q)
+    for parity in (0, 1):
+        _, wf = _maps(q, shape, fluid, c, opp, parity)
+        written = set(wf) | set(_filler_writes(q, shape, fluid, c, opp, parity, sector, True))
+        for z in range(nz):
+            for y in range(ny):
+                for x in range(nx):
+                    assert all(((z, y, x), i) in written for i in range(q)), (parity, z, y, x)
