@@ -260,6 +260,24 @@ def main():
         from paper_2506_09242_amd import inputs as _inp
         derived["percolates_x"] = bool(_inp.percolates_x(tags))
 
+    if args.workload.startswith("tgv"):
+        # convective time t_c = N / (2 pi u0); dissipation eps = -dk/dt by central
+        # differences of the FP64 k series; eps* = eps t_c / u0^2
+        n, u0 = tags.shape[0], wl_cfg["u0"]
+        tc = n / (2 * np.pi * u0)
+        for pn, r in results.items():
+            t = np.array([m_["step"] for m_ in r["series"]], dtype=np.float64)
+            k = np.array([m_["kinetic_energy"] for m_ in r["series"]])
+            if len(t) < 3:
+                continue
+            eps = -np.gradient(k, t) * tc / u0 ** 2
+            j = int(np.argmax(eps))
+            stride = max(1, int(round(0.5 * tc / max(t[1] - t[0], 1.0))))
+            derived[pn] = {"t_c_steps": tc, "eps_peak_tc": float(t[j] / tc), "eps_peak_nondim": float(eps[j]),
+                           "k_final_over_k0": float(k[-1] / k[0]),
+                           "t_over_tc": [round(float(v / tc), 3) for v in t[::stride]],
+                           "eps_nondim": [float(v) for v in eps[::stride]]}
+
     main_p = prec_names[0]
     m = results[main_p]
     traffic = stored_traffic(args.workload, main_p)

@@ -124,7 +124,11 @@ size_t lbm_population_bytes(const lbm_config *cfg);
  * kernel variant covering the models present (Sec. 2.3, kernel-size
  * reduction).  hip_stream: hipStream_t to launch on, NULL = null stream.
  * The library allocates and owns the population array.  Populations are
- * undefined until lbm_init_equilibrium or lbm_write_populations.
+ * undefined until lbm_init_equilibrium or lbm_write_populations.  Besides
+ * the populations the handle owns nx*ny*nz bytes of tags, 4*nx*ny*nz bytes
+ * of per-node neighbour masks when the lattice has non-fluid nodes or more
+ * than one fluid model, and a few per-tile words.  The slots of non-fluid
+ * nodes hold unspecified values: a step may overwrite them.
  * Errors: EINVAL (config or tags), ENOMEM, EHIP. */
 lbm_status lbm_create(const lbm_config *cfg, const uint8_t *tags_host, void *hip_stream,
                       lbm_lattice **out);
