@@ -112,9 +112,11 @@ typedef struct lbm_lattice lbm_lattice;
 
 /* ---------------------------------------------------------------- lattice */
 
-/* Bytes of device memory one lattice's population array needs for cfg
- * (Q slots of a padded plane of nx*ny*nz cells in the storage precision;
- * the in-place AA scheme needs one array, Sec. 2.3 notes it halves the
+/* Bytes of device memory one lattice's population array needs for cfg:
+ * Q populations of every node in the storage precision, nodes rounded up to
+ * whole blocks of 4096 (the array is blocked by node index: each block of
+ * 4096 consecutive nodes stores its Q slots one after another).  The
+ * in-place AA scheme needs one array (Sec. 2.3 notes it halves the
  * two-population footprint).  Returns 0 if cfg is invalid. */
 size_t lbm_population_bytes(const lbm_config *cfg);
 

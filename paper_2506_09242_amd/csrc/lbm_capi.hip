@@ -40,7 +40,7 @@ struct lbm_lattice {
     double *d_wall = nullptr;       // [16][3]
     void *d_pops = nullptr;
     bool own_pops = false;
-    long long stride = 0;           // elements per slot
+    long long n_elems = 0;          // population array elements
     long long ncell = 0;
     double *d_partials = nullptr;   // [NRED][max_tiles]
     long long max_tiles = 0;
@@ -110,10 +110,9 @@ Launchers pick(int q, int prec) {
 
 size_t elem_bytes(int prec) { return prec == LBM_F64 ? 8 : (prec == LBM_F32 ? 4 : 2); }
 
-// Slot stride: the plane rounded up to 128 elements plus 128 more, so every
-// slot starts 256-byte aligned and slot bases never sit a power of two apart
-// (which would put all Q streams of a node on the same HBM channel).
-long long slot_stride(long long ncell) { return (ncell + 127) / 128 * 128 + 128; }
+// Population array elements: whole blocks of kBlockNodes nodes, Q slots each
+// (the blocked layout of pop_base).
+long long pop_elems(long long ncell, int q) { return (ncell + kBlockNodes - 1) / kBlockNodes * kBlockNodes * q; }
 
 bool known_tag(int t) { return (t >= 0 && t <= 4) || (t >= 16 && t <= 31); }
 
@@ -189,7 +188,6 @@ StepParams step_params(const lbm_lattice *L) {
     p.wall_u = L->d_wall;
     p.partials = L->d_partials;
     p.partial_stride = L->max_tiles;
-    p.stride = L->stride;
     p.nx = c.nx;
     p.ny = c.ny;
     p.nz = c.nz;
@@ -217,7 +215,6 @@ AuxParams aux_params(const lbm_lattice *L) {
     AuxParams a{};
     a.pops = L->d_pops;
     a.tags = L->d_tags;
-    a.stride = L->stride;
     a.nx = L->cfg.nx;
     a.ny = L->cfg.ny;
     a.nz = L->cfg.nz;
@@ -367,7 +364,7 @@ hipError_t launch_finalize(const double *partials, long long partial_stride, int
 extern "C" size_t lbm_population_bytes(const lbm_config *cfg) {
     if (validate(cfg) != LBM_OK) return 0;
     const long long n = (long long)cfg->nx * cfg->ny * cfg->nz;
-    return (size_t)cfg->q * (size_t)slot_stride(n) * elem_bytes(cfg->prec);
+    return (size_t)pop_elems(n, cfg->q) * elem_bytes(cfg->prec);
 }
 
 static lbm_status create_impl(const lbm_config *cfg, const uint8_t *tags_host, void *pops_dev, size_t pops_bytes,
@@ -426,7 +423,7 @@ static lbm_status create_impl(const lbm_config *cfg, const uint8_t *tags_host, v
     L->cfg = *cfg;
     L->stream = static_cast<hipStream_t>(stream);
     L->ncell = N;
-    L->stride = slot_stride(N);
+    L->n_elems = pop_elems(N, cfg->q);
     L->n_fluid = nf;
     L->ms = ms;
     L->tagged = tagged;

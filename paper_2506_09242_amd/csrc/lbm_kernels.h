@@ -226,8 +226,8 @@ __global__ __launch_bounds__(256) void k_collide_stream(StepParams p) {
     // Node class.  Tiles whose one-node halo is a single fluid model (the
     // interior of a walled domain) need nothing; the other tiles read each
     // node's precomputed neighbour mask (block-uniform branch).
-    const long long st = p.stride;
     S *__restrict__ f = static_cast<S *>(p.pops);
+    const long long pb = pop_base<Q>(n);
     int tag = p.uniform_tag;
     uint32_t wall = 0;   // bit i: node x + c_i is not fluid
     bool moving = false; // some neighbour is a moving wall
@@ -265,13 +265,14 @@ __global__ __launch_bounds__(256) void k_collide_stream(StepParams p) {
             using Vi = V<Q, i>;
             long long off;
             if constexpr (PARITY == 0 || i == 0) {
-                off = (long long)i * st + n;
+                off = pb + slot_off(i);
             } else {
                 // direction i arrives from x - c_i (slot opp), or from the node's
                 // own slot i when x - c_i is a wall
-                const long long o_nb = (long long)Vi::opp * st + (zo[1 - Vi::z] + yo[1 - Vi::y] + xo[1 - Vi::x]);
+                const long long o_nb =
+                    pop_base<Q>(zo[1 - Vi::z] + yo[1 - Vi::y] + xo[1 - Vi::x]) + slot_off(Vi::opp);
                 if constexpr (TAGGED) {
-                    off = ((wall >> Vi::opp) & 1u) ? (long long)i * st + n : o_nb;
+                    off = ((wall >> Vi::opp) & 1u) ? pb + slot_off(i) : o_nb;
                 } else {
                     off = o_nb;
                 }
@@ -323,18 +324,18 @@ __global__ __launch_bounds__(256) void k_collide_stream(StepParams p) {
                 long long off;
                 bool ok = true;
                 if constexpr (i == 0) {
-                    off = n;
+                    off = pb;
                 } else if constexpr (PARITY == 0) {
                     // even step: h*_i goes to slot opp(i) of the node itself
-                    off = (long long)Vi::opp * st + n;
+                    off = pb + slot_off(Vi::opp);
                 } else {
                     // odd step: h*_i goes to slot i of x + c_i, or back to slot
                     // opp(i) of the node itself when x + c_i is a wall
-                    off = (long long)i * st + (zo[1 + Vi::z] + yo[1 + Vi::y] + xo[1 + Vi::x]);
+                    off = pop_base<Q>(zo[1 + Vi::z] + yo[1 + Vi::y] + xo[1 + Vi::x]) + slot_off(i);
                     if constexpr (TAGGED) {
                         const bool wi = (wall >> i) & 1u;
-                        if (wi) off = live ? (long long)Vi::opp * st + n
-                                           : (long long)i * st + (zo[1 + Vi::z] + yo[1 + Vi::y] + xo[1]);
+                        if (wi) off = live ? pb + slot_off(Vi::opp)
+                                           : pop_base<Q>(zo[1 + Vi::z] + yo[1 + Vi::y] + xo[1]) + slot_off(i);
                         ok = live || wi;
                     }
                 }
@@ -430,7 +431,7 @@ __global__ __launch_bounds__(256) void k_init(AuxParams a) {
         using Vi = V<Q, i>;
         const double cu = Vi::x * ux + Vi::y * uy + Vi::z * uz;
         const double heq = Vi::w * (drho + rho * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
-        f[(long long)i * a.stride + n] = (S)heq;
+        f[pop_base<Q>((int)n) + slot_off(i)] = (S)heq;
     });
 }
 
@@ -444,11 +445,11 @@ __device__ __forceinline__ void load_natural(const AuxParams &a, long long n, do
     sfor<Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         using Vi = V<Q, i>;
-        long long off = (long long)i * a.stride + n;
+        long long off = pop_base<Q>((int)n) + slot_off(i);
         if (a.parity != 0 && i != 0) {
             const int sx = wrap_idx(x - Vi::x, nx), sy = wrap_idx(y - Vi::y, ny), sz = wrap_idx(z - Vi::z, nz);
             const long long src = ((long long)sz * ny + sy) * nx + sx;
-            if (is_fluid_tag(a.tags[src])) off = (long long)Vi::opp * a.stride + src;
+            if (is_fluid_tag(a.tags[src])) off = pop_base<Q>((int)src) + slot_off(Vi::opp);
         }
         fo[i] = a.shifted ? (double)f[off] : (double)f[off] + Vi::w * a.rho0;
     });
@@ -502,7 +503,7 @@ __global__ __launch_bounds__(256) void k_scatter(AuxParams a) {
         constexpr int i = decltype(I)::value;
         using Vi = V<Q, i>;
         const double v = a.in_f[(long long)i * a.count + t];
-        f[(long long)i * a.stride + n] = (S)(a.shifted ? v : v - Vi::w * a.rho0);
+        f[pop_base<Q>((int)n) + slot_off(i)] = (S)(a.shifted ? v : v - Vi::w * a.rho0);
     });
 }
 

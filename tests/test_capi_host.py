@@ -52,12 +52,11 @@ def test_velocity_table_matches_oracle_order(q):
 
 def test_population_bytes():
     for q, prec, s in [(19, lbm.LBM_F64, 8), (19, lbm.LBM_F32, 4), (27, lbm.LBM_F16S, 2)]:
-        cfg = lbm.make_config(10, 7, 3, q=q, prec=prec)
-        nb = lbm.lbm_population_bytes(cfg)
-        N = 210
-        stride = (N + 127) // 128 * 128 + 128
-        assert nb == q * stride * s
-        assert (stride * s) % 256 == 0
+        for dims in [(10, 7, 3), (64, 64, 1), (64, 64, 2), (100, 50, 9)]:
+            cfg = lbm.make_config(*dims, q=q, prec=prec)
+            N = dims[0] * dims[1] * dims[2]
+            # whole blocks of 4096 nodes, Q slots each
+            assert lbm.lbm_population_bytes(cfg) == -(-N // 4096) * 4096 * q * s
     bad = lbm.make_config(0, 1, 1)
     assert lbm.lbm_population_bytes(bad) == 0
 
