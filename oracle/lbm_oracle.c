@@ -21,6 +21,10 @@
  *     decouples wall position from the relaxation time).
  *   - Smagorinsky subgrid model (Fig. 3 / Sec. 2.3 list it among the chained
  *     models), in the implicit relaxation-time form.
+ *   - Regularized BGK (the regularized family the paper's robust RR model
+ *     belongs to, Sec. 3.1-3.2): the non-equilibrium part is replaced by its
+ *     projection on the second-order Hermite polynomials before relaxing
+ *     (Latt and Chopard's regularization, textbook form with Guo forcing).
  *   - Standard and modified (moving-wall) bounce-back (Sec. 3 intro: Ladd's
  *     Dirichlet conditions).
  *   - Guo body force (not in the paper; drives the porous case).
@@ -58,9 +62,9 @@ typedef struct {
 } orc_config;
 
 /* Tag values (fixed interface shared with the C ABI). */
-enum { T_SOLID = 0, T_BGK = 1, T_TRT = 2, T_SMAG = 3, T_MLP = 4, T_WALL0 = 16 };
+enum { T_SOLID = 0, T_BGK = 1, T_TRT = 2, T_SMAG = 3, T_MLP = 4, T_REG = 5, T_WALL0 = 16 };
 
-static int is_fluid(int t) { return t >= 1 && t <= 4; }
+static int is_fluid(int t) { return t >= 1 && t <= 5; }
 
 /* ------------------------------------------------------------------ tables */
 /*
@@ -249,7 +253,33 @@ static void collide_node(const orc_config *cfg, const lattice_t *L, int tag,
         tau = tau_eff;
     }
 
-    if (tag == T_TRT) {
+    if (tag == T_REG) {
+        /* Regularized BGK.  With Guo forcing the populations read
+         *   f = feq + f1 - F_i/2,
+         * f1 the first-order (Chapman-Enskog) non-equilibrium part, whose
+         * second moment is Pi1 = sum c c (f - feq) + (u F + F u)/2.  The
+         * regularization keeps only the second-order Hermite projection of f1,
+         *   f1_i = w_i / (2 cs^4) (c_i c_i - cs^2 I) : Pi1   (cs^2 = 1/3),
+         * and BGK with the Guo source on f = feq + f1 - F_i/2 gives
+         *   f*_i = feq_i + (1 - 1/tau) f1_i + F_i/2. */
+        double Pi1[3][3];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) Pi1[a][b] = 0.5 * (u[a] * F[b] + F[a] * u[b]);
+        for (int i = 0; i < q; ++i) {
+            double d = fin[i] - feq[i];
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) Pi1[a][b] += L->c[i][a] * L->c[i][b] * d;
+        }
+        const double cs2 = 1.0 / 3.0;
+        for (int i = 0; i < q; ++i) {
+            double qpi = 0.0;
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b)
+                    qpi += (L->c[i][a] * L->c[i][b] - (a == b ? cs2 : 0.0)) * Pi1[a][b];
+            double f1 = L->w[i] / (2.0 * cs2 * cs2) * qpi;
+            fout[i] = feq[i] + (1.0 - 1.0 / tau) * f1 + 0.5 * (Fev[i] + Fod[i]);
+        }
+    } else if (tag == T_TRT) {
         double wp = 1.0 / tau;
         double taum = 0.5 + cfg->trt_lambda / (tau - 0.5);
         double wm = 1.0 / taum;

@@ -89,7 +89,7 @@ def _node(q=19, **kw):
 
 
 @pytest.mark.parametrize("q", [19, 27])
-@pytest.mark.parametrize("tag", [oracle.TAG_BGK, oracle.TAG_TRT, oracle.TAG_SMAG])
+@pytest.mark.parametrize("tag", [oracle.TAG_BGK, oracle.TAG_TRT, oracle.TAG_SMAG, oracle.TAG_REG])
 def test_collision_conserves_mass_and_adds_force(q, tag):
     """sum f* = sum f and sum c f* = sum c f + F (Guo forcing), any model."""
     c, w, _ = oracle.tables(q)
@@ -120,7 +120,7 @@ def test_rest_equilibrium_is_fixed_point():
     for q in (19, 27):
         o = _node(q, tau=0.6)
         f = oracle.equilibrium(q, 1.0, [0, 0, 0])
-        for tag in (oracle.TAG_BGK, oracle.TAG_TRT, oracle.TAG_SMAG):
+        for tag in (oracle.TAG_BGK, oracle.TAG_TRT, oracle.TAG_SMAG, oracle.TAG_REG):
             fo, _ = o.collide_node(tag, f)
             assert np.abs(fo - f).max() < 4e-16
 
@@ -137,6 +137,85 @@ def test_trt_reduces_to_bgk(q):
     a, _ = o.collide_node(oracle.TAG_TRT, f)
     b, _ = o.collide_node(oracle.TAG_BGK, f)
     assert np.allclose(a, b, rtol=0, atol=1e-16)
+
+
+def _guo_source(q, u, F):
+    """Guo's forcing populations F_i = w_i [3 (c_i - u).F + 9 (c_i.u)(c_i.F)]."""
+    c, w, _ = oracle.tables(q)
+    cu, cF = c @ u, c @ F
+    return w * (3.0 * (c @ F - np.dot(u, F)) + 9.0 * cu * cF)
+
+
+def _hermite2(q, Pi):
+    """w_i / (2 cs^4) (c_i c_i - cs^2 I) : Pi, cs^2 = 1/3."""
+    c, w, _ = oracle.tables(q)
+    Qi = np.einsum("ia,ib->iab", c, c) - np.eye(3)[None] / 3.0
+    return w * 4.5 * np.einsum("iab,ab->i", Qi, Pi)
+
+
+@pytest.mark.parametrize("q", [19, 27])
+def test_regularized_equals_bgk_on_second_order_nonequilibrium(q):
+    """If the non-equilibrium part already is a second-order Hermite term,
+    f = feq + g - F_i/2 with g = w Q:Pi / (2 cs^4), regularizing changes nothing:
+    the regularized model equals BGK (any tau, with force)."""
+    rng = np.random.default_rng(21)
+    F = np.array([3e-5, -1e-5, 2e-5])
+    o = _node(q, tau=0.71, force=F)
+    for _ in range(5):
+        rho, u = 1.0 + 0.03 * rng.standard_normal(), 0.04 * rng.standard_normal(3)
+        A = 1e-3 * rng.standard_normal((3, 3))
+        f = oracle.equilibrium(q, rho, u) + _hermite2(q, A + A.T) - 0.5 * _guo_source(q, u, F)
+        a, _ = o.collide_node(oracle.TAG_REG, f)
+        b, _ = o.collide_node(oracle.TAG_BGK, f)
+        assert np.abs(a - b).max() < 2e-16
+
+
+@pytest.mark.parametrize("q", [19, 27])
+def test_regularized_keeps_second_moment_and_filters_the_rest(q):
+    """For a general non-equilibrium state the regularized model gives the same
+    post-collision density, momentum and momentum flux as BGK, and its
+    post-collision non-equilibrium part (f* - feq - F_i/2) is a pure
+    second-order Hermite term; at tau = 1 it equals BGK."""
+    c, w, _ = oracle.tables(q)
+    rng = np.random.default_rng(22)
+    F = np.array([-2e-5, 1e-5, 4e-5])
+    for tau in (0.64, 1.0, 1.7):
+        o = _node(q, tau=tau, force=F)
+        f = oracle.equilibrium(q, 1.02, [0.03, -0.02, 0.01]) + 2e-3 * w * rng.standard_normal(q)
+        a, _ = o.collide_node(oracle.TAG_REG, f)
+        b, _ = o.collide_node(oracle.TAG_BGK, f)
+        for k in (0, 1, 2):
+            ma = np.einsum("i,ia,ib->ab", a, c, c) if k == 2 else (a @ c if k == 1 else a.sum())
+            mb = np.einsum("i,ia,ib->ab", b, c, c) if k == 2 else (b @ c if k == 1 else b.sum())
+            assert np.abs(np.asarray(ma) - np.asarray(mb)).max() < 1e-15
+        rho = f.sum()
+        u = (f @ c + 0.5 * F) / rho
+        r = a - oracle.equilibrium(q, rho, u) - 0.5 * _guo_source(q, u, F)
+        Pi = np.einsum("i,ia,ib->ab", r, c, c)
+        assert np.abs(r - _hermite2(q, Pi)).max() < 1e-15
+        if tau == 1.0:
+            assert np.abs(a - b).max() < 1e-16
+        else:
+            assert np.abs(a - b).max() > 1e-7  # BGK keeps the higher-order part
+
+
+def test_regularized_couette_and_shear_decay():
+    """Couette flow with the regularized model is exactly linear with half-way
+    walls (the steady non-equilibrium part is a pure second-order term), and a
+    z-invariant Taylor-Green vortex decays at 4 nu k^2 to O(k^2)."""
+    nz, U = 12, 0.02
+    for tau in (0.7, 1.3):
+        tags = inputs.channel_tags(1, 1, nz, top=inputs.TAG_WALL0)
+        tags = np.where(tags == oracle.TAG_BGK, oracle.TAG_REG, tags).astype(np.uint8)
+        o = oracle.Oracle(1, 1, nz, q=19, tau=tau, tags=tags, wall_velocity=[(U, 0, 0)])
+        o.init_equilibrium()
+        o.run(8000)
+        _, u = o.fields()
+        z = np.arange(1, nz - 1)
+        assert np.abs(u[0, 1:-1, 0, 0] - U * (z - 0.5) / (nz - 2)).max() < 1e-10 * U
+    e32 = _tgv2d_rate(32, 0.01, 0.8, 100, tag=oracle.TAG_REG)
+    e64 = _tgv2d_rate(64, 0.01, 0.8, 400, tag=oracle.TAG_REG)
+    assert e32 < 2e-2 and e32 / e64 >= 3.0
 
 
 @pytest.mark.parametrize("q", [19, 27])
@@ -346,9 +425,9 @@ def test_cavity_conserves_mass():
     assert m["momentum"][0] > 1e-3
 
 
-def _tgv2d_rate(n, u0, tau, steps):
+def _tgv2d_rate(n, u0, tau, steps, tag=oracle.TAG_BGK):
     rho, u = inputs.tgv2d_fields(n, 1, u0)
-    o = oracle.Oracle(n, n, 1, q=19, tau=tau)
+    o = oracle.Oracle(n, n, 1, q=19, tau=tau, tags=np.full((1, n, n), tag, np.uint8))
     o.init_equilibrium(rho, u)
     t, k = [], []
     for s in range(0, steps + 1, 10):
