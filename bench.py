@@ -5,7 +5,8 @@ solid shell, lid moving at u = 0.1, Re = 1000 over the 254-cell cavity),
 FP32 shifted-population storage.  One "step" is one fused collide+stream
 update of the whole lattice (even and odd AA steps alternate) with the FP64
 domain reductions sampled every 100 steps (fused into the step).  Inputs are
-resident in HBM before timing starts.  The same run is repeated in FP64 and
+resident in HBM before timing starts.  The timed run is repeated three times
+back to back and the median is reported.  The same run is repeated in FP64 and
 FP16 storage; their MLUPS, roofline fractions and the kinetic-energy /
 velocity error against the FP64 run are reported alongside.
 
@@ -29,6 +30,7 @@ METRIC = "MLUPS and % of HBM roofline per dtype at 1 GPU; energy error vs FP64"
 WORKLOADS = {
     # name: (builder, q, description)
     "cavity256_d3q19_bgk": "D3Q19 BGK lid-driven cavity 256^3, lid u=0.1, Re=1000",
+    "cavity256_d3q19_reg": "D3Q19 regularized-BGK lid-driven cavity 256^3, lid u=0.1, Re=1000",
     "tgv512_d3q27_smag": "D3Q27 BGK+Smagorinsky(Cs=0.1) Taylor-Green 512^3, u0=0.05, Re=1600",
     "porous400_d3q19_trt": "D3Q19 TRT(3/16) body-force porous 400^3, phi=0.20, corr. length 8",
     "tgv32_d3q19_bgk": "D3Q19 BGK Taylor-Green 32^3, u0=0.04, Re=100 (cache-resident)",
@@ -55,6 +57,13 @@ def build_workload(name):
         tags = inputs.cavity_tags(n)
         kw = dict(q=19, tau=3 * nu + 0.5, wall_velocity=[(0.1, 0.0, 0.0)])
         return tags, kw, None, None, {"cells": n ** 3, "lid_u": 0.1, "Re": 1000, "cavity_length": L}
+    if name == "cavity256_d3q19_reg":
+        n = 256
+        L = n - 2
+        nu = 0.1 * L / 1000.0
+        tags = inputs.cavity_tags(n, fluid_tag=inputs.TAG_REG)
+        kw = dict(q=19, tau=3 * nu + 0.5, wall_velocity=[(0.1, 0.0, 0.0)])
+        return tags, kw, None, None, {"cells": n ** 3, "lid_u": 0.1, "Re": 1000, "cavity_length": L}
     if name == "tgv512_d3q27_smag":
         n, u0, Re = 512, 0.05, 1600.0
         nu = u0 * (n / (2 * np.pi)) / Re
@@ -79,14 +88,16 @@ def build_workload(name):
 def alg_bytes_per_launch(tags, q, prec_bytes):
     """Algorithmic HBM bytes of one collide-stream launch: every fluid node reads
     and writes its Q populations once; every node's tag byte is read once."""
-    fluid = int(np.isin(tags, (1, 2, 3, 4)).sum())
+    fluid = int(np.isin(tags, (1, 2, 3, 4, 5)).sum())
     return fluid * 2 * q * prec_bytes + tags.size, fluid
 
 
-def run_dtype(tags, kw, rho, u, prec, steps, warmup, every, chunk=2000, label=""):
-    """Time `steps` steps (reductions every `every`, fused) after `warmup`.  Long
-    runs go in chunks of about `chunk` steps (a multiple of `every`) with one
-    progress line each; the events bracket all chunks."""
+def run_dtype(tags, kw, rho, u, prec, steps, warmup, every, repeats=1, chunk=2000, label=""):
+    """Time `steps` steps (reductions every `every`, fused) after `warmup`, `repeats`
+    times back to back on the same lattice.  Long runs go in chunks of about
+    `chunk` steps (a multiple of `every`) with one progress line each; the events
+    bracket all chunks of one repeat.  The series and the final fields are those
+    of the first repeat (state after warmup + steps)."""
     import torch
     from paper_2506_09242_amd import lbm
     stream = torch.cuda.current_stream()
@@ -94,29 +105,33 @@ def run_dtype(tags, kw, rho, u, prec, steps, warmup, every, chunk=2000, label=""
     L.init_equilibrium(rho, u)
     if warmup:
         L.step(warmup)
-    L.synchronize()
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
     chunk = max(every, chunk // every * every)
-    t0 = time.perf_counter()
-    e0.record(stream)
-    series, done = [], 0
-    while done < steps:
-        n = min(chunk, steps - done)
-        part = L.step_reduce(n, every)  # synchronizes at its end
-        series.extend(part if not series else part[1:])
-        done += n
-        if steps > chunk:
-            print(f"# {label}: {done}/{steps} steps, {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = e0.elapsed_time(e1)
-    _, uf = L.read_fields()
+    runs, first = [], None
+    for rep in range(repeats):
+        L.synchronize()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        series, done = [], 0
+        while done < steps:
+            n = min(chunk, steps - done)
+            part = L.step_reduce(n, every)  # synchronizes at its end
+            series.extend(part if not series else part[1:])
+            done += n
+            if steps > chunk:
+                print(f"# {label}: {done}/{steps} steps, {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+                      flush=True)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        runs.append(e0.elapsed_time(e1))
+        if rep == 0:
+            _, uf = L.read_fields()
+            first = {"wall_s": time.perf_counter() - t0, "series": series, "u": uf}
     variant = L.variant
     L.close()
-    return {"ms": ms, "wall_s": wall, "series": series, "u": uf, "variant": variant}
+    return dict(first, ms=float(np.median(runs)), runs_ms=runs, variant=variant)
 
 
 def cpu_baseline(name, tags, kw, rho, u, steps):
@@ -152,6 +167,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--every", type=int, default=100, help="reduction sampling period (steps)")
+    ap.add_argument("--repeats", type=int, default=3, help="timed runs per dtype; the median is reported")
     ap.add_argument("--workload", default="cavity256_d3q19_bgk", choices=sorted(WORKLOADS))
     ap.add_argument("--dtypes", default="f32,f64,f16s", help="first one is the reported value")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -209,7 +225,7 @@ def main():
     results = {}
     for pn in prec_names:
         prec = lbm.PREC_NAMES[pn]
-        r = run_dtype(tags, kw, rho, u, prec, args.steps, args.warmup, args.every, label=pn)
+        r = run_dtype(tags, kw, rho, u, prec, args.steps, args.warmup, args.every, args.repeats, label=pn)
         nbytes, nfluid = alg_bytes_per_launch(tags, kw["q"], lbm.PREC_BYTES[prec])
         launch_s = r["ms"] * 1e-3 / args.steps
         achieved = nbytes / launch_s / 1e9
@@ -218,6 +234,7 @@ def main():
                        "ms_per_step": r["ms"] / args.steps,
                        "alg_GBps": achieved, "hbm_frac": achieved / HBM_PEAK_GBS,
                        "bytes_per_launch": nbytes, "variant": r["variant"],
+                       "runs_ms_per_step": [round(v / args.steps, 5) for v in r["runs_ms"]],
                        "k_final": r["series"][-1]["kinetic_energy"], "series": r["series"], "u": r["u"],
                        "wall_s": r["wall_s"]}
         print(f"# {pn}: {results[pn]['MLUPS']:.1f} MLUPS, {achieved:.1f} GB/s algorithmic "
@@ -254,7 +271,7 @@ def main():
             ux_mean = r["series"][-1]["velocity_sum"][0] / tags.size
             k_lu = nu * ux_mean / F
             derived[pn] = {"permeability_lu": k_lu, "permeability_mD": k_lu * (5.345e-6) ** 2 / 9.869233e-16,
-                           "porosity": float(np.isin(tags, (1, 2, 3, 4)).mean()),
+                           "porosity": float(np.isin(tags, (1, 2, 3, 4, 5)).mean()),
                            "steps_total": args.warmup + args.steps,
                            "k_series_lu": [nu * m["velocity_sum"][0] / tags.size / F for m in r["series"][::20]]}
         from paper_2506_09242_amd import inputs as _inp
@@ -299,7 +316,8 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "per_dtype": {pn: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()
-                           if k in ("MLUPS", "MFLUPS_fluid", "ms_per_step", "alg_GBps", "hbm_frac", "variant")}
+                           if k in ("MLUPS", "MFLUPS_fluid", "ms_per_step", "alg_GBps", "hbm_frac", "variant",
+                                    "runs_ms_per_step")}
                       for pn, r in results.items()},
         "error_vs_fp64": errors,
         "derived": derived,

@@ -79,6 +79,10 @@ enum {
     LBM_TAG_TRT = 2,       /* two-relaxation-time, magic parameter trt_lambda   */
     LBM_TAG_BGK_SMAG = 3,  /* BGK + Smagorinsky eddy viscosity (implicit tau)  */
     LBM_TAG_BGK_MLP = 4,   /* BGK + learned eddy viscosity, Smagorinsky fallback */
+    LBM_TAG_REG = 5,       /* regularized BGK: the non-equilibrium part is replaced
+                              by its second-order Hermite projection before
+                              relaxing (the regularized family of the paper's
+                              robust RR model, Sec. 3.1-3.2)                  */
     LBM_TAG_WALL0 = 16     /* 16..31: moving wall, velocity wall_velocity[tag-16] */
 };
 

@@ -21,13 +21,14 @@ enum ModelSet : int {
     MS_TRT = 2,
     MS_SMAG = 4,
     MS_MLP = 8,
+    MS_REG = 16,
 };
 
 // Compiled model-set variants, smallest first.  The host picks the first one
 // that covers the fluid tags present.
-constexpr int kModelSets[] = {MS_BGK, MS_TRT, MS_BGK | MS_SMAG, MS_BGK | MS_SMAG | MS_MLP,
-                              MS_BGK | MS_TRT | MS_SMAG | MS_MLP};
-constexpr int kNumModelSets = 5;
+constexpr int kModelSets[] = {MS_BGK, MS_TRT, MS_REG, MS_BGK | MS_SMAG, MS_BGK | MS_SMAG | MS_MLP,
+                              MS_BGK | MS_TRT | MS_SMAG | MS_MLP | MS_REG};
+constexpr int kNumModelSets = 6;
 
 // Kernel modes.
 enum StepMode : int {

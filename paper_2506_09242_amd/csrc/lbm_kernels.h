@@ -130,9 +130,9 @@ __device__ __forceinline__ void collide_node(const C (&h)[Q], int tag, bool live
     if constexpr ((MS & MS_TRT) != 0) {
         if (tag == LBM_TAG_TRT) wm = (C)p.omega_minus;
     }
-    if constexpr ((MS & (MS_SMAG | MS_MLP)) != 0) {
-        // Pi_ab = sum c_a c_b (h - heq): only even parts contribute.
-        C pxx = C(0), pyy = C(0), pzz = C(0), pxy = C(0), pxz = C(0), pyz = C(0);
+    // Pi_ab = sum c_a c_b (h - heq): only even parts contribute.
+    C pxx = C(0), pyy = C(0), pzz = C(0), pxy = C(0), pxz = C(0), pyz = C(0);
+    if constexpr ((MS & (MS_SMAG | MS_MLP | MS_REG)) != 0) {
         sfor<H>([&](auto K) {
             constexpr int k = decltype(K)::value + 1;
             using Vk = V<Q, k>;
@@ -144,6 +144,8 @@ __device__ __forceinline__ void collide_node(const C (&h)[Q], int tag, bool live
             if constexpr (Vk::x * Vk::z != 0) pxz += C(Vk::x * Vk::z) * ne;
             if constexpr (Vk::y * Vk::z != 0) pyz += C(Vk::y * Vk::z) * ne;
         });
+    }
+    if constexpr ((MS & (MS_SMAG | MS_MLP)) != 0) {
         const C qn = sqrt(pxx * pxx + pyy * pyy + pzz * pzz + C(2) * (pxy * pxy + pxz * pxz + pyz * pyz));
         const C tau0 = (C)p.tau;
         const C tau_s = C(0.5) * (tau0 + sqrt(tau0 * tau0 + (C)p.smag_c * qn * inv_rho));
@@ -167,9 +169,34 @@ __device__ __forceinline__ void collide_node(const C (&h)[Q], int tag, bool live
         }
     }
 
+    // Regularized BGK (second-order Hermite projection of the first-order
+    // non-equilibrium part, Guo forcing).  The populations read
+    // f = feq + f1 - F_i/2, f1 having the momentum flux Pi1 = Pi + (uF + Fu)/2;
+    // relaxing feq + w_i Q_i:Pi1 / (2 cs^4) - F_i/2 gives
+    //   f*_i = feq_i + (1 - omega) w_i (9/2) (c_i.Pi1.c_i - tr Pi1 / 3) + F_i / 2,
+    // which is the omega = 1 update below (A, B) plus the regularized term added
+    // to the even part of each pair.
+    C reg = C(0);  // (1 - omega) * 9/2 on regularized nodes, else 0
+    C rxx = C(0), ryy = C(0), rzz = C(0), rxy = C(0), rxz = C(0), ryz = C(0), rtr = C(0);
+    if constexpr ((MS & MS_REG) != 0) {
+        if (tag == LBM_TAG_REG) {
+            reg = (C(1) - (C)p.omega) * C(4.5);
+            wp = C(1);
+            wm = C(1);
+        }
+        rxx = pxx + ux * Fx;
+        ryy = pyy + uy * Fy;
+        rzz = pzz + uz * Fz;
+        rxy = pxy + C(0.5) * (ux * Fy + uy * Fx);
+        rxz = pxz + C(0.5) * (ux * Fz + uz * Fx);
+        ryz = pyz + C(0.5) * (uy * Fz + uz * Fy);
+        rtr = (rxx + ryy + rzz) * C(1.0 / 3.0);
+    }
+
     const C gp = C(1) - C(0.5) * wp, gm = C(1) - C(0.5) * wm;
     const C F0 = C(V<Q, 0>::w) * C(-3) * uF;
     hs[0] = h[0] - wp * (h[0] - ev[0]) + gp * F0;
+    if constexpr ((MS & MS_REG) != 0) hs[0] -= reg * C(V<Q, 0>::w) * rtr;
     sfor<H>([&](auto K) {
         constexpr int k = decltype(K)::value + 1;
         using Vk = V<Q, k>;
@@ -181,8 +208,18 @@ __device__ __forceinline__ void collide_node(const C (&h)[Q], int tag, bool live
         const C Fo = C(Vk::w) * C(3) * cF;
         const C hp = C(0.5) * (h[k] + h[k + H]);
         const C hm = C(0.5) * (h[k] - h[k + H]);
-        const C A = gp * Fe - wp * (hp - ev[k]);
+        C A = gp * Fe - wp * (hp - ev[k]);
         const C B = gm * Fo - wm * (hm - od[k]);
+        if constexpr ((MS & MS_REG) != 0) {
+            C cpc = C(0);  // c_k . Pi1 . c_k
+            if constexpr (Vk::x != 0) cpc += rxx;
+            if constexpr (Vk::y != 0) cpc += ryy;
+            if constexpr (Vk::z != 0) cpc += rzz;
+            if constexpr (Vk::x * Vk::y != 0) cpc += C(2 * Vk::x * Vk::y) * rxy;
+            if constexpr (Vk::x * Vk::z != 0) cpc += C(2 * Vk::x * Vk::z) * rxz;
+            if constexpr (Vk::y * Vk::z != 0) cpc += C(2 * Vk::y * Vk::z) * ryz;
+            A += reg * C(Vk::w) * (cpc - rtr);
+        }
         hs[k] = h[k] + A + B;
         hs[k + H] = h[k + H] + A - B;
     });
@@ -542,8 +579,9 @@ hipError_t launch_step(const StepParams &p, int ms, bool tagged, int mode, int p
         case MS_BGK | MS_SMAG: return launch_step_geo<Q, P, MS_BGK | MS_SMAG>(p, tagged, mode, parity, s);
         case MS_BGK | MS_SMAG | MS_MLP:
             return launch_step_geo<Q, P, MS_BGK | MS_SMAG | MS_MLP>(p, tagged, mode, parity, s);
-        case MS_BGK | MS_TRT | MS_SMAG | MS_MLP:
-            return launch_step_geo<Q, P, MS_BGK | MS_TRT | MS_SMAG | MS_MLP>(p, tagged, mode, parity, s);
+        case MS_REG: return launch_step_geo<Q, P, MS_REG>(p, tagged, mode, parity, s);
+        case MS_BGK | MS_TRT | MS_SMAG | MS_MLP | MS_REG:
+            return launch_step_geo<Q, P, MS_BGK | MS_TRT | MS_SMAG | MS_MLP | MS_REG>(p, tagged, mode, parity, s);
         default: return hipErrorInvalidValue;
     }
 }

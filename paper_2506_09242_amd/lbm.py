@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(_HERE, "liblbm_hip.so")
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EHIP, LBM_EUNSTABLE, LBM_EUNSUPPORTED, LBM_ESTATE = 0, -1, -2, -3, -4, -5, -6
 LBM_F64, LBM_F32, LBM_F16S = 0, 1, 2
-TAG_SOLID, TAG_BGK, TAG_TRT, TAG_SMAG, TAG_MLP, TAG_WALL0 = 0, 1, 2, 3, 4, 16
+TAG_SOLID, TAG_BGK, TAG_TRT, TAG_SMAG, TAG_MLP, TAG_REG, TAG_WALL0 = 0, 1, 2, 3, 4, 5, 16
 MLP_NPARAMS = 1359
 PREC_NAMES = {"f64": LBM_F64, "f32": LBM_F32, "f16s": LBM_F16S}
 PREC_BYTES = {LBM_F64: 8, LBM_F32: 4, LBM_F16S: 2}
