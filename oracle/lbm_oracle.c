@@ -21,6 +21,13 @@
  *     decouples wall position from the relaxation time).
  *   - Smagorinsky subgrid model (Fig. 3 / Sec. 2.3 list it among the chained
  *     models), in the implicit relaxation-time form.
+ *   - Regularized open boundaries on the x planes (Sec. 3.3: the Berea runs
+ *     drive the flow by regularized velocity / pressure conditions, after
+ *     Latt et al. 2008): the populations entering through the plane are
+ *     rebuilt from the imposed velocity (density from mass and normal
+ *     momentum balance) or the imposed density (normal velocity likewise),
+ *     with the non-equilibrium part of each unknown population taken from
+ *     its opposite, then the whole node is regularized and relaxed.
  *   - Regularized BGK (the regularized family the paper's robust RR model
  *     belongs to, Sec. 3.1-3.2): the non-equilibrium part is replaced by its
  *     projection on the second-order Hermite polynomials before relaxing
@@ -56,15 +63,18 @@ typedef struct {
     double smag_cs;     /* Smagorinsky constant                             */
     double force[3];    /* uniform body-force density                       */
     double wall_u[16][3]; /* velocity of moving-wall tags 16..31            */
+    double bc_u[3];     /* velocity imposed on inlet nodes (tag 6)          */
+    double bc_rho;      /* density imposed on outlet nodes (tag 7)          */
     int32_t flags;      /* bit0: skip collision (free streaming, test only) */
     int32_t pad;
     const float *mlp;   /* packed MLP parameters (see below), may be NULL   */
 } orc_config;
 
 /* Tag values (fixed interface shared with the C ABI). */
-enum { T_SOLID = 0, T_BGK = 1, T_TRT = 2, T_SMAG = 3, T_MLP = 4, T_REG = 5, T_WALL0 = 16 };
+enum { T_SOLID = 0, T_BGK = 1, T_TRT = 2, T_SMAG = 3, T_MLP = 4, T_REG = 5, T_VIN = 6, T_POUT = 7,
+       T_WALL0 = 16 };
 
-static int is_fluid(int t) { return t >= 1 && t <= 5; }
+static int is_fluid(int t) { return t >= 1 && t <= 7; }
 
 /* ------------------------------------------------------------------ tables */
 /*
@@ -221,6 +231,56 @@ static void collide_node(const orc_config *cfg, const lattice_t *L, int tag,
 
     if (cfg->flags & 1) { /* free streaming: no collision */
         for (int i = 0; i < q; ++i) fout[i] = fin[i];
+        return;
+    }
+
+    if (tag == T_VIN || tag == T_POUT) {
+        /* Open boundary on an x plane.  Inlet (x = 0): the populations with
+         * c_x = +1 come from outside; the velocity is imposed and the density
+         * follows from mass and x-momentum over the known populations,
+         *   rho (1 - u_x) = sum_{c_x=0} f + 2 sum_{c_x=-1} f.
+         * Outlet (x = nx-1): the populations with c_x = -1 are unknown; the
+         * density is imposed, u_y = u_z = 0 and
+         *   u_x = (sum_{c_x=0} f + 2 sum_{c_x=+1} f) / rho - 1. */
+        const int inlet = tag == T_VIN;
+        double s0 = 0.0, sp = 0.0, sm = 0.0;
+        for (int i = 0; i < q; ++i) {
+            if (L->c[i][0] == 0) s0 += fin[i];
+            else if (L->c[i][0] > 0) sp += fin[i];
+            else sm += fin[i];
+        }
+        double rb, ub[3];
+        if (inlet) {
+            for (int a = 0; a < 3; ++a) ub[a] = cfg->bc_u[a];
+            rb = (s0 + 2.0 * sm) / (1.0 - ub[0]);
+        } else {
+            rb = cfg->bc_rho;
+            ub[0] = (s0 + 2.0 * sp) / rb - 1.0;
+            ub[1] = ub[2] = 0.0;
+        }
+        double fb[ORC_MAXQ], fe[ORC_MAXQ];
+        equilibrium(L, rb, ub, fe);
+        for (int i = 0; i < q; ++i) {
+            const int unknown = inlet ? L->c[i][0] > 0 : L->c[i][0] < 0;
+            /* unknown: equilibrium plus the opposite population's non-equilibrium part */
+            fb[i] = unknown ? fe[i] + (fin[L->opp[i]] - fe[L->opp[i]]) : fin[i];
+        }
+        /* regularize the completed node, then relax (BGK; its non-equilibrium
+         * part is even in c, so a TRT node relaxes the same way) */
+        double Pi[3][3] = {{0}};
+        for (int i = 0; i < q; ++i) {
+            double d = fb[i] - fe[i];
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) Pi[a][b] += L->c[i][a] * L->c[i][b] * d;
+        }
+        const double cs2 = 1.0 / 3.0;
+        for (int i = 0; i < q; ++i) {
+            double qpi = 0.0;
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b)
+                    qpi += (L->c[i][a] * L->c[i][b] - (a == b ? cs2 : 0.0)) * Pi[a][b];
+            fout[i] = fe[i] + (1.0 - 1.0 / cfg->tau) * L->w[i] / (2.0 * cs2 * cs2) * qpi;
+        }
         return;
     }
 

@@ -478,3 +478,87 @@ def test_enstrophy_taylor_green():
     assert abs(oracle.enstrophy(u) / (3 * u0 * u0 * _kmod(k) ** 2 / 8.0) - 1.0) < 1e-12
     # and the stencil is accurate: k' = k (1 - O(k^8))
     assert abs(_kmod(k) / k - 1.0) < 1e-5
+
+
+# ------------------------------------------------- regularized open boundaries
+def _open_node_input(q, tag, rng, rho, u, F=None):
+    """Known populations of an equilibrium + second-order (even) Hermite state;
+    the populations entering through the boundary plane are random garbage."""
+    c, w, _ = oracle.tables(q)
+    A = 1e-3 * rng.standard_normal((3, 3))
+    g = _hermite2(q, A + A.T)
+    f = oracle.equilibrium(q, rho, u) + g
+    unknown = c[:, 0] > 0 if tag == oracle.TAG_VIN else c[:, 0] < 0
+    f[unknown] = rng.uniform(0.0, 0.2, int(unknown.sum()))
+    return f, g
+
+
+@pytest.mark.parametrize("q", [19, 27])
+def test_open_boundary_node_rebuilds_equilibrium_plus_nonequilibrium(q):
+    """An inlet (outlet) node whose known populations are feq(rho, u) + g, g an even
+    second-order Hermite term, relaxes to feq + (1 - 1/tau) g with the imposed
+    velocity (density) and the density (normal velocity) that mass and momentum
+    balance give, whatever the populations entering through the plane hold."""
+    rng = np.random.default_rng(31)
+    tau = 0.74
+    for _ in range(4):
+        rho, U = 1.0 + 0.02 * rng.standard_normal(), np.array([0.03, 0.01, -0.02])
+        o = _node(q, tau=tau, bc_velocity=U)
+        f, g = _open_node_input(q, oracle.TAG_VIN, rng, rho, U)
+        fo, _ = o.collide_node(oracle.TAG_VIN, f)
+        assert np.abs(fo - (oracle.equilibrium(q, rho, U) + (1 - 1 / tau) * g)).max() < 1e-15
+        rho_out, ux = 1.0 + 0.02 * rng.standard_normal(), 0.04 * rng.standard_normal()
+        o = _node(q, tau=tau, bc_density=rho_out)
+        f, g = _open_node_input(q, oracle.TAG_POUT, rng, rho_out, [ux, 0.0, 0.0])
+        fo, _ = o.collide_node(oracle.TAG_POUT, f)
+        assert np.abs(fo - (oracle.equilibrium(q, rho_out, [ux, 0, 0]) + (1 - 1 / tau) * g)).max() < 1e-15
+
+
+def _open_channel_tags(nx, ny, nz, walls):
+    t = inputs.channel_tags(nx, ny, nz, fluid_tag=oracle.TAG_TRT) if walls else \
+        inputs.all_fluid(nx, ny, nz, oracle.TAG_TRT)
+    t[:, :, 0] = np.where(t[:, :, 0] == oracle.TAG_TRT, oracle.TAG_VIN, t[:, :, 0])
+    t[:, :, -1] = np.where(t[:, :, -1] == oracle.TAG_TRT, oracle.TAG_POUT, t[:, :, -1])
+    return t
+
+
+def test_open_boundaries_keep_uniform_flow():
+    """Uniform flow through an open periodic-in-y,z duct with inlet velocity U and
+    outlet density 1 is a fixed point of the scheme."""
+    nx, ny, nz, U = 12, 3, 4, np.array([0.05, 0.0, 0.0])
+    tags = _open_channel_tags(nx, ny, nz, walls=False)
+    o = oracle.Oracle(nx, ny, nz, q=19, tau=0.7, tags=tags, bc_velocity=U, bc_density=1.0)
+    u0 = np.zeros((3, nz, ny, nx))
+    u0[0] = U[0]
+    o.init_equilibrium(None, u0)
+    f0 = o.f.copy()
+    o.run(60)
+    inner = tags == oracle.TAG_TRT
+    assert np.abs(o.f[:, inner] - f0[:, inner]).max() < 1e-15
+
+
+def test_open_channel_reaches_poiseuille():
+    """Velocity inlet (uniform U) and pressure outlet (rho = 1) between resting walls,
+    TRT with Lambda = 3/16: far from the inlet the flow is the Poiseuille profile
+    whose pressure gradient is 12 nu rho U_m / H^2 (c_s^2 drho/dx), the mass flux is
+    the same through every interior plane, and the profile is the parabola."""
+    nx, ny, nz, U, tau = 96, 1, 18, 0.01, 0.8
+    H = nz - 2
+    tags = _open_channel_tags(nx, ny, nz, walls=True)
+    o = oracle.Oracle(nx, ny, nz, q=19, tau=tau, tags=tags, bc_velocity=(U, 0, 0), bc_density=1.0)
+    u0 = np.zeros((3, nz, ny, nx))
+    u0[0] = U * (tags != 0)
+    o.init_equilibrium(None, u0)
+    o.run(20000)
+    rho, u = o.fields()
+    flux = (rho * u[0])[1:-1, 0, 1:-1].sum(0)
+    assert np.abs(flux / flux.mean() - 1).max() < 1e-3
+    nu = (tau - 0.5) / 3.0
+    Um = flux.mean() / H
+    x = np.arange(nx)
+    sel = (x > 30) & (x < 80)
+    slope = np.polyfit(x[sel], rho[1:-1, 0, :].mean(0)[sel], 1)[0]
+    assert abs(slope / (-36.0 * nu * Um / H ** 2) - 1.0) < 1e-2
+    z = np.arange(1, nz - 1) - 0.5
+    prof = u[0, 1:-1, 0, 60] * rho[1:-1, 0, 60]
+    assert np.abs(prof - 6.0 * Um * z * (H - z) / H ** 2).max() < 1e-2 * 1.5 * Um
