@@ -88,7 +88,7 @@ def build_workload(name):
 def alg_bytes_per_launch(tags, q, prec_bytes):
     """Algorithmic HBM bytes of one collide-stream launch: every fluid node reads
     and writes its Q populations once; every node's tag byte is read once."""
-    fluid = int(np.isin(tags, (1, 2, 3, 4, 5)).sum())
+    fluid = int(np.isin(tags, (1, 2, 3, 4, 5, 6, 7)).sum())
     return fluid * 2 * q * prec_bytes + tags.size, fluid
 
 
@@ -271,7 +271,7 @@ def main():
             ux_mean = r["series"][-1]["velocity_sum"][0] / tags.size
             k_lu = nu * ux_mean / F
             derived[pn] = {"permeability_lu": k_lu, "permeability_mD": k_lu * (5.345e-6) ** 2 / 9.869233e-16,
-                           "porosity": float(np.isin(tags, (1, 2, 3, 4, 5)).mean()),
+                           "porosity": float(np.isin(tags, (1, 2, 3, 4, 5, 6, 7)).mean()),
                            "steps_total": args.warmup + args.steps,
                            "k_series_lu": [nu * m["velocity_sum"][0] / tags.size / F for m in r["series"][::20]]}
         from paper_2506_09242_amd import inputs as _inp

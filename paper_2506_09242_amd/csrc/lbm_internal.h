@@ -22,13 +22,14 @@ enum ModelSet : int {
     MS_SMAG = 4,
     MS_MLP = 8,
     MS_REG = 16,
+    MS_OPEN = 32,  // regularized velocity inlet / pressure outlet nodes
 };
 
 // Compiled model-set variants, smallest first.  The host picks the first one
 // that covers the fluid tags present.
-constexpr int kModelSets[] = {MS_BGK, MS_TRT, MS_REG, MS_BGK | MS_SMAG, MS_BGK | MS_SMAG | MS_MLP,
-                              MS_BGK | MS_TRT | MS_SMAG | MS_MLP | MS_REG};
-constexpr int kNumModelSets = 6;
+constexpr int kModelSets[] = {MS_BGK, MS_TRT, MS_REG, MS_BGK | MS_SMAG, MS_TRT | MS_OPEN, MS_BGK | MS_SMAG | MS_MLP,
+                              MS_BGK | MS_TRT | MS_SMAG | MS_MLP | MS_REG | MS_OPEN};
+constexpr int kNumModelSets = 7;
 
 // Kernel modes.
 enum StepMode : int {
@@ -80,6 +81,8 @@ struct StepParams {
     double smag_c;            // 18 sqrt(2) Cs^2 (implicit Smagorinsky)
     double nu0;               // (tau - 1/2) / 3
     double force[3];
+    double bc_u[3];           // velocity imposed on inlet nodes
+    double bc_rho;            // density imposed on outlet nodes
     MlpDev mlp;
 };
 

@@ -82,6 +82,90 @@ __device__ __forceinline__ void node_reduce(const C (&h)[Q], bool live, const St
     red[9] += (live && !ok) ? 1.0 : 0.0;
 }
 
+// Regularized open boundary on an x plane (the conditions of Latt et al. 2008
+// the paper uses for the Berea runs, Sec. 3.3), shifted form: f_i = h_i + w_i rho0.
+// Inlet (x = 0): populations with c_x = +1 enter from outside; the velocity is
+// imposed and the density follows from mass and x-momentum over the known ones,
+//   rho (1 - u_x) = sum_{c_x=0} f + 2 sum_{c_x=-1} f = s0 + 2 s- + rho0
+// (the weights of c_x = 0 plus twice those of c_x = -1 sum to 1).  Outlet
+// (x = nx-1): populations with c_x = -1 are unknown, the density is imposed,
+// u_y = u_z = 0 and u_x = (s0 + 2 s+ + rho0) / rho - 1.  Each unknown population
+// is equilibrium plus its opposite's non-equilibrium part; the node is then
+// regularized (Hermite projection of its momentum flux) and relaxed with omega.
+// No body force on these nodes.
+template <int Q, typename C>
+__device__ __forceinline__ void open_boundary(const C (&h)[Q], int tag, const StepParams &p, C (&hs)[Q]) {
+    const bool inlet = tag == LBM_TAG_VEL_IN;
+    C s0 = C(0), sp = C(0), sm = C(0);
+    sfor<Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        using Vi = V<Q, i>;
+        if constexpr (Vi::x == 0) s0 += h[i];
+        if constexpr (Vi::x > 0) sp += h[i];
+        if constexpr (Vi::x < 0) sm += h[i];
+    });
+    const C rho0 = (C)p.rho0;
+    C rb, ux, uy, uz;
+    if (inlet) {
+        ux = (C)p.bc_u[0];
+        uy = (C)p.bc_u[1];
+        uz = (C)p.bc_u[2];
+        rb = (s0 + C(2) * sm + rho0) / (C(1) - ux);
+    } else {
+        rb = (C)p.bc_rho;
+        ux = (s0 + C(2) * sp + rho0) / rb - C(1);
+        uy = C(0);
+        uz = C(0);
+    }
+    const C drb = rb - rho0;
+    const C uu = ux * ux + uy * uy + uz * uz;
+    C he[Q];
+    sfor<Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        using Vi = V<Q, i>;
+        C cu = C(0);
+        if constexpr (Vi::x != 0) cu += C(Vi::x) * ux;
+        if constexpr (Vi::y != 0) cu += C(Vi::y) * uy;
+        if constexpr (Vi::z != 0) cu += C(Vi::z) * uz;
+        he[i] = C(Vi::w) * (drb + rb * (C(3) * cu + C(4.5) * cu * cu - C(1.5) * uu));
+    });
+    // non-equilibrium part of the completed node; an unknown population takes
+    // its opposite's
+    C pxx = C(0), pyy = C(0), pzz = C(0), pxy = C(0), pxz = C(0), pyz = C(0);
+    sfor<Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        using Vi = V<Q, i>;
+        if constexpr (i > 0) {
+            constexpr int o = Vi::opp;
+            C ne = h[i] - he[i];
+            if constexpr (Vi::x != 0) {
+                const bool unknown = inlet ? (Vi::x > 0) : (Vi::x < 0);
+                if (unknown) ne = h[o] - he[o];
+            }
+            if constexpr (Vi::x != 0) pxx += ne;
+            if constexpr (Vi::y != 0) pyy += ne;
+            if constexpr (Vi::z != 0) pzz += ne;
+            if constexpr (Vi::x * Vi::y != 0) pxy += C(Vi::x * Vi::y) * ne;
+            if constexpr (Vi::x * Vi::z != 0) pxz += C(Vi::x * Vi::z) * ne;
+            if constexpr (Vi::y * Vi::z != 0) pyz += C(Vi::y * Vi::z) * ne;
+        }
+    });
+    const C tr = (pxx + pyy + pzz) * C(1.0 / 3.0);
+    const C a = (C(1) - (C)p.omega) * C(4.5);
+    sfor<Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        using Vi = V<Q, i>;
+        C cpc = C(0);
+        if constexpr (Vi::x != 0) cpc += pxx;
+        if constexpr (Vi::y != 0) cpc += pyy;
+        if constexpr (Vi::z != 0) cpc += pzz;
+        if constexpr (Vi::x * Vi::y != 0) cpc += C(2 * Vi::x * Vi::y) * pxy;
+        if constexpr (Vi::x * Vi::z != 0) cpc += C(2 * Vi::x * Vi::z) * pxz;
+        if constexpr (Vi::y * Vi::z != 0) cpc += C(2 * Vi::y * Vi::z) * pyz;
+        hs[i] = he[i] + a * C(Vi::w) * (cpc - tr);
+    });
+}
+
 // Collision of one node in shifted form (pair split, Guo forcing).  Every lane
 // of the wave must call it (the learned closure is evaluated wave-wide).
 template <int Q, typename C, int MS>
@@ -223,6 +307,10 @@ __device__ __forceinline__ void collide_node(const C (&h)[Q], int tag, bool live
         hs[k] = h[k] + A + B;
         hs[k + H] = h[k + H] + A - B;
     });
+
+    if constexpr ((MS & MS_OPEN) != 0) {
+        if (tag == LBM_TAG_VEL_IN || tag == LBM_TAG_PRES_OUT) open_boundary<Q, C>(h, tag, p, hs);
+    }
 }
 
 // The fused collide-and-stream step: one thread per node, 256-thread blocks
@@ -580,8 +668,10 @@ hipError_t launch_step(const StepParams &p, int ms, bool tagged, int mode, int p
         case MS_BGK | MS_SMAG | MS_MLP:
             return launch_step_geo<Q, P, MS_BGK | MS_SMAG | MS_MLP>(p, tagged, mode, parity, s);
         case MS_REG: return launch_step_geo<Q, P, MS_REG>(p, tagged, mode, parity, s);
-        case MS_BGK | MS_TRT | MS_SMAG | MS_MLP | MS_REG:
-            return launch_step_geo<Q, P, MS_BGK | MS_TRT | MS_SMAG | MS_MLP | MS_REG>(p, tagged, mode, parity, s);
+        case MS_TRT | MS_OPEN: return launch_step_geo<Q, P, MS_TRT | MS_OPEN>(p, tagged, mode, parity, s);
+        case MS_BGK | MS_TRT | MS_SMAG | MS_MLP | MS_REG | MS_OPEN:
+            return launch_step_geo<Q, P, MS_BGK | MS_TRT | MS_SMAG | MS_MLP | MS_REG | MS_OPEN>(p, tagged, mode,
+                                                                                              parity, s);
         default: return hipErrorInvalidValue;
     }
 }

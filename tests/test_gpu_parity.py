@@ -131,6 +131,45 @@ def test_regularized_cavity_and_force_fp64(q, steps):
     assert err <= TOL
 
 
+def _open_channel(nx, ny, nz, bulk):
+    t = inputs.channel_tags(nx, ny, nz, fluid_tag=bulk)
+    t[:, :, 0] = np.where(t[:, :, 0] == bulk, inputs.TAG_VIN, t[:, :, 0])
+    t[:, :, -1] = np.where(t[:, :, -1] == bulk, inputs.TAG_POUT, t[:, :, -1])
+    return t
+
+
+@pytest.mark.parametrize("q,steps", [(19, 301), (27, 120)])
+def test_open_boundaries_channel_fp64(q, steps):
+    """Regularized velocity inlet and pressure outlet between resting walls (TRT
+    bulk, the trt+open kernel), developing channel flow."""
+    tags = _open_channel(40, 5, 12, inputs.TAG_TRT)
+    rho, u = inputs.random_fields(40, 5, 12, seed=41, du=0.0)
+    o, L = make_pair(tags, q=q, tau=0.8, bc_velocity=(0.04, 0.0, 0.005), bc_density=1.01, rho=rho, u=u)
+    assert L.variant == f"D3Q{q}/f64/trt+open/tagged"
+    L.step(steps)
+    o.run(steps)
+    err = max_rel_pop_error(L.read_populations(), o.f, tags)
+    _print("open channel", q, steps, err)
+    assert err <= TOL
+
+
+def test_open_boundaries_with_every_model_fp64():
+    """Open boundaries in the all-model kernel: regularized bulk, a moving lid and a
+    body force (not applied on the boundary nodes)."""
+    tags = _open_channel(33, 4, 10, inputs.TAG_REG)
+    tags[-1, :, 1:-1] = inputs.TAG_WALL0
+    tags[3:6, 1:3, 15] = inputs.TAG_SMAG
+    tags[3:6, 1:3, 20] = inputs.TAG_BGK
+    o, L = make_pair(tags, q=19, tau=0.7, smag_cs=0.12, force=(2e-6, 0, 0), bc_velocity=(0.03, 0, 0),
+                     bc_density=1.0, wall_velocity=[(0.02, 0, 0)])
+    assert L.variant.endswith("/all/tagged")
+    L.step(151)
+    o.run(151)
+    err = max_rel_pop_error(L.read_populations(), o.f, tags)
+    _print("open all", err)
+    assert err <= TOL
+
+
 def test_tgv_d3q27_smagorinsky_fp64():
     n = 24
     rho, u = inputs.tgv3d_fields(n, 0.05)
