@@ -34,6 +34,8 @@ WORKLOADS = {
     "tgv512_d3q27_smag": "D3Q27 BGK+Smagorinsky(Cs=0.1) Taylor-Green 512^3, u0=0.05, Re=1600",
     "porous400_d3q19_trt": "D3Q19 TRT(3/16) body-force porous 400^3, phi=0.20, corr. length 8",
     "tgv32_d3q19_bgk": "D3Q19 BGK Taylor-Green 32^3, u0=0.04, Re=100 (cache-resident)",
+    "porous480_open_d3q19_trt": "D3Q19 TRT(3/16) porous 400^3 rock between 40-plane buffers, regularized "
+                                "velocity inlet / pressure outlet (480x400x400)",
     "closure_tgv128_d3q27": "learned closure: D3Q27 TGV Re=1600, fine 512^3 -> coarse 128^3, MLP vs Smagorinsky vs BGK",
 }
 
@@ -76,6 +78,18 @@ def build_workload(name):
         tags = inputs.porous_tags(n, porosity=0.20, ell=8.0, seed=42)
         kw = dict(q=19, tau=1.0, trt_lambda=3.0 / 16.0, force=(1e-5, 0.0, 0.0))
         return tags, kw, None, None, {"cells": n ** 3, "porosity": 0.2, "seed": 42}
+    if name == "porous480_open_d3q19_trt":
+        # the paper's Berea layout (Sec. 3.3): 40 fluid planes upstream, the
+        # 400^3 rock, 40 downstream; regularized velocity inlet at x = 0 and
+        # pressure outlet at x = nx-1; periodic in y and z
+        n, buf = 400, 40
+        tags = np.full((n, n, n + 2 * buf), inputs.TAG_TRT, dtype=np.uint8)
+        tags[:, :, buf:buf + n] = inputs.porous_tags(n, porosity=0.20, ell=8.0, seed=42)
+        tags[:, :, 0] = inputs.TAG_VIN
+        tags[:, :, -1] = inputs.TAG_POUT
+        kw = dict(q=19, tau=1.0, trt_lambda=3.0 / 16.0, bc_velocity=(5e-6, 0.0, 0.0), bc_density=1.0)
+        return tags, kw, None, None, {"cells": tags.size, "porosity": 0.2, "seed": 42, "buffer": buf,
+                                      "rock": n, "inlet_u": 5e-6}
     if name == "tgv32_d3q19_bgk":
         n, u0 = 32, 0.04
         rho, u = inputs.tgv3d_fields(n, u0)
@@ -92,7 +106,7 @@ def alg_bytes_per_launch(tags, q, prec_bytes):
     return fluid * 2 * q * prec_bytes + tags.size, fluid
 
 
-def run_dtype(tags, kw, rho, u, prec, steps, warmup, every, repeats=1, chunk=2000, label=""):
+def run_dtype(tags, kw, rho, u, prec, steps, warmup, every, repeats=1, chunk=2000, label="", keep_rho=False):
     """Time `steps` steps (reductions every `every`, fused) after `warmup`, `repeats`
     times back to back on the same lattice.  Long runs go in chunks of about
     `chunk` steps (a multiple of `every`) with one progress line each; the events
@@ -127,8 +141,10 @@ def run_dtype(tags, kw, rho, u, prec, steps, warmup, every, repeats=1, chunk=200
         torch.cuda.synchronize()
         runs.append(e0.elapsed_time(e1))
         if rep == 0:
-            _, uf = L.read_fields()
+            rf, uf = L.read_fields()
             first = {"wall_s": time.perf_counter() - t0, "series": series, "u": uf}
+            if keep_rho:
+                first["rho"] = rf
     variant = L.variant
     L.close()
     return dict(first, ms=float(np.median(runs)), runs_ms=runs, variant=variant)
@@ -225,7 +241,8 @@ def main():
     results = {}
     for pn in prec_names:
         prec = lbm.PREC_NAMES[pn]
-        r = run_dtype(tags, kw, rho, u, prec, args.steps, args.warmup, args.every, args.repeats, label=pn)
+        r = run_dtype(tags, kw, rho, u, prec, args.steps, args.warmup, args.every, args.repeats, label=pn,
+                      keep_rho=args.workload == "porous480_open_d3q19_trt")
         nbytes, nfluid = alg_bytes_per_launch(tags, kw["q"], lbm.PREC_BYTES[prec])
         launch_s = r["ms"] * 1e-3 / args.steps
         achieved = nbytes / launch_s / 1e9
@@ -236,6 +253,7 @@ def main():
                        "bytes_per_launch": nbytes, "variant": r["variant"],
                        "runs_ms_per_step": [round(v / args.steps, 5) for v in r["runs_ms"]],
                        "k_final": r["series"][-1]["kinetic_energy"], "series": r["series"], "u": r["u"],
+                       "rho": r.get("rho"),
                        "wall_s": r["wall_s"]}
         print(f"# {pn}: {results[pn]['MLUPS']:.1f} MLUPS, {achieved:.1f} GB/s algorithmic "
               f"({100 * achieved / HBM_PEAK_GBS:.1f}% of 8 TB/s), {r['variant']}", file=sys.stderr, flush=True)
@@ -276,6 +294,26 @@ def main():
                            "k_series_lu": [nu * m["velocity_sum"][0] / tags.size / F for m in r["series"][::20]]}
         from paper_2506_09242_amd import inputs as _inp
         derived["percolates_x"] = bool(_inp.percolates_x(tags))
+
+    if args.workload == "porous480_open_d3q19_trt":
+        # Darcy permeability from the pressure drop across the rock (Eq. 6):
+        # k = u_mean nu L / dP, u_mean over every rock node (solids 0), dP = cs^2
+        # (mean fluid density of the plane before the rock - of the plane after it)
+        nu = (kw["tau"] - 0.5) / 3.0
+        buf, n = wl_cfg["buffer"], wl_cfg["rock"]
+        fl = np.isin(tags, (1, 2, 3, 4, 5, 6, 7))
+        for pn, r in results.items():
+            ux = r["u"][0]
+            u_mean = float(ux[:, :, buf:buf + n].mean())
+            rho_f = r["rho"]
+            r_up = float(rho_f[:, :, buf - 1][fl[:, :, buf - 1]].mean())
+            r_dn = float(rho_f[:, :, buf + n][fl[:, :, buf + n]].mean())
+            dP = (r_up - r_dn) / 3.0
+            k_lu = u_mean * nu * n / dP
+            derived[pn] = {"permeability_lu": k_lu, "permeability_mD": k_lu * (5.345e-6) ** 2 / 9.869233e-16,
+                           "u_mean_rock": u_mean, "rho_upstream": r_up, "rho_downstream": r_dn,
+                           "steps_total": args.warmup + args.steps}
+            del r["rho"]
 
     if args.workload.startswith("tgv"):
         # convective time t_c = N / (2 pi u0); dissipation eps = -dk/dt by central
