@@ -18,7 +18,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
-TAG_SOLID, TAG_BGK, TAG_TRT, TAG_SMAG, TAG_MLP, TAG_REG, TAG_VIN, TAG_POUT, TAG_WALL0 = 0, 1, 2, 3, 4, 5, 6, 7, 16
+TAG_SOLID, TAG_BGK, TAG_TRT, TAG_SMAG, TAG_MLP, TAG_REG, TAG_WALL0 = 0, 1, 2, 3, 4, 5, 16
+TAG_VIN, TAG_POUT, TAG_PIN, TAG_VOUT = 6, 7, 8, 9  # open boundaries on the x planes
 MLP_PARAMS = 1359
 
 
@@ -26,7 +27,7 @@ class OrcConfig(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("q", C.c_int32),
                 ("rho0", C.c_double), ("tau", C.c_double), ("trt_lambda", C.c_double),
                 ("smag_cs", C.c_double), ("force", C.c_double * 3),
-                ("wall_u", (C.c_double * 3) * 16), ("bc_u", C.c_double * 3), ("bc_rho", C.c_double),
+                ("wall_u", (C.c_double * 3) * 16), ("bc_u", C.c_double * 3), ("bc_rho", C.c_double * 2),
                 ("flags", C.c_int32), ("pad", C.c_int32),
                 ("mlp", C.POINTER(C.c_float))]
 
@@ -87,7 +88,7 @@ class Oracle:
 
     def __init__(self, nx, ny, nz, q=19, tau=0.8, rho0=1.0, trt_lambda=3.0 / 16.0, smag_cs=0.0,
                  force=(0.0, 0.0, 0.0), wall_velocity=None, tags=None, free_streaming=False,
-                 mlp=None, bc_velocity=(0.0, 0.0, 0.0), bc_density=1.0):
+                 mlp=None, bc_velocity=(0.0, 0.0, 0.0), bc_density=(1.0, 1.0)):
         self.cfg = OrcConfig()
         self.cfg.nx, self.cfg.ny, self.cfg.nz, self.cfg.q = nx, ny, nz, q
         self.cfg.rho0, self.cfg.tau, self.cfg.trt_lambda, self.cfg.smag_cs = rho0, tau, trt_lambda, smag_cs
@@ -99,7 +100,7 @@ class Oracle:
                     self.cfg.wall_u[k][a] = v[a]
         for a in range(3):
             self.cfg.bc_u[a] = bc_velocity[a]
-        self.cfg.bc_rho = bc_density
+        self.cfg.bc_rho[0], self.cfg.bc_rho[1] = bc_density
         self.cfg.flags = 1 if free_streaming else 0
         self._mlp = None
         if mlp is not None:

@@ -63,18 +63,21 @@ typedef struct {
     double smag_cs;     /* Smagorinsky constant                             */
     double force[3];    /* uniform body-force density                       */
     double wall_u[16][3]; /* velocity of moving-wall tags 16..31            */
-    double bc_u[3];     /* velocity imposed on inlet nodes (tag 6)          */
-    double bc_rho;      /* density imposed on outlet nodes (tag 7)          */
+    double bc_u[3];     /* velocity imposed on velocity-boundary nodes      */
+    double bc_rho[2];   /* density imposed on pressure-boundary nodes at    */
+                        /* x = 0 ([0]) and x = nx-1 ([1])                   */
     int32_t flags;      /* bit0: skip collision (free streaming, test only) */
     int32_t pad;
     const float *mlp;   /* packed MLP parameters (see below), may be NULL   */
 } orc_config;
 
 /* Tag values (fixed interface shared with the C ABI). */
+/* Open boundaries: T_VIN velocity at x = 0, T_POUT pressure at x = nx-1,
+ * T_PIN pressure at x = 0, T_VOUT velocity at x = nx-1. */
 enum { T_SOLID = 0, T_BGK = 1, T_TRT = 2, T_SMAG = 3, T_MLP = 4, T_REG = 5, T_VIN = 6, T_POUT = 7,
-       T_WALL0 = 16 };
+       T_PIN = 8, T_VOUT = 9, T_WALL0 = 16 };
 
-static int is_fluid(int t) { return t >= 1 && t <= 7; }
+static int is_fluid(int t) { return t >= 1 && t <= 9; }
 
 /* ------------------------------------------------------------------ tables */
 /*
@@ -234,34 +237,37 @@ static void collide_node(const orc_config *cfg, const lattice_t *L, int tag,
         return;
     }
 
-    if (tag == T_VIN || tag == T_POUT) {
-        /* Open boundary on an x plane.  Inlet (x = 0): the populations with
-         * c_x = +1 come from outside; the velocity is imposed and the density
-         * follows from mass and x-momentum over the known populations,
-         *   rho (1 - u_x) = sum_{c_x=0} f + 2 sum_{c_x=-1} f.
-         * Outlet (x = nx-1): the populations with c_x = -1 are unknown; the
-         * density is imposed, u_y = u_z = 0 and
-         *   u_x = (sum_{c_x=0} f + 2 sum_{c_x=+1} f) / rho - 1. */
-        const int inlet = tag == T_VIN;
+    if (tag >= T_VIN && tag <= T_VOUT) {
+        /* Open boundary on an x plane.  On the x = 0 plane the populations with
+         * c_x = +1 come from outside, on the x = nx-1 plane those with c_x = -1.
+         * Mass and x-momentum over the known populations give, with s = -1 at
+         * x = 0 and s = +1 at x = nx-1,
+         *   rho (1 + s u_x) = sum_{c_x=0} f + 2 sum_{c_x=s} f = K,
+         * so a velocity boundary (u imposed) has rho = K / (1 + s u_x) and a
+         * pressure boundary (rho imposed, u_y = u_z = 0) has u_x = s (K/rho - 1). */
+        const int low = tag == T_VIN || tag == T_PIN;   /* the x = 0 plane */
+        const int vel = tag == T_VIN || tag == T_VOUT;  /* velocity imposed */
+        const double sg = low ? -1.0 : 1.0;
         double s0 = 0.0, sp = 0.0, sm = 0.0;
         for (int i = 0; i < q; ++i) {
             if (L->c[i][0] == 0) s0 += fin[i];
             else if (L->c[i][0] > 0) sp += fin[i];
             else sm += fin[i];
         }
+        const double K = s0 + 2.0 * (low ? sm : sp);
         double rb, ub[3];
-        if (inlet) {
+        if (vel) {
             for (int a = 0; a < 3; ++a) ub[a] = cfg->bc_u[a];
-            rb = (s0 + 2.0 * sm) / (1.0 - ub[0]);
+            rb = K / (1.0 + sg * ub[0]);
         } else {
-            rb = cfg->bc_rho;
-            ub[0] = (s0 + 2.0 * sp) / rb - 1.0;
+            rb = cfg->bc_rho[low ? 0 : 1];
+            ub[0] = sg * (K / rb - 1.0);
             ub[1] = ub[2] = 0.0;
         }
         double fb[ORC_MAXQ], fe[ORC_MAXQ];
         equilibrium(L, rb, ub, fe);
         for (int i = 0; i < q; ++i) {
-            const int unknown = inlet ? L->c[i][0] > 0 : L->c[i][0] < 0;
+            const int unknown = low ? L->c[i][0] > 0 : L->c[i][0] < 0;
             /* unknown: equilibrium plus the opposite population's non-equilibrium part */
             fb[i] = unknown ? fe[i] + (fin[L->opp[i]] - fe[L->opp[i]]) : fin[i];
         }

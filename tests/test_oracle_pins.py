@@ -481,53 +481,59 @@ def test_enstrophy_taylor_green():
 
 
 # ------------------------------------------------- regularized open boundaries
-def _open_node_input(q, tag, rng, rho, u, F=None):
+_LOW = {oracle.TAG_VIN: True, oracle.TAG_PIN: True, oracle.TAG_POUT: False, oracle.TAG_VOUT: False}
+
+
+def _open_node_input(q, tag, rng, rho, u):
     """Known populations of an equilibrium + second-order (even) Hermite state;
     the populations entering through the boundary plane are random garbage."""
     c, w, _ = oracle.tables(q)
     A = 1e-3 * rng.standard_normal((3, 3))
     g = _hermite2(q, A + A.T)
     f = oracle.equilibrium(q, rho, u) + g
-    unknown = c[:, 0] > 0 if tag == oracle.TAG_VIN else c[:, 0] < 0
+    unknown = c[:, 0] > 0 if _LOW[tag] else c[:, 0] < 0
     f[unknown] = rng.uniform(0.0, 0.2, int(unknown.sum()))
     return f, g
 
 
 @pytest.mark.parametrize("q", [19, 27])
-def test_open_boundary_node_rebuilds_equilibrium_plus_nonequilibrium(q):
-    """An inlet (outlet) node whose known populations are feq(rho, u) + g, g an even
+@pytest.mark.parametrize("tag", [oracle.TAG_VIN, oracle.TAG_POUT, oracle.TAG_PIN, oracle.TAG_VOUT])
+def test_open_boundary_node_rebuilds_equilibrium_plus_nonequilibrium(q, tag):
+    """A boundary node whose known populations are feq(rho, u) + g, g an even
     second-order Hermite term, relaxes to feq + (1 - 1/tau) g with the imposed
     velocity (density) and the density (normal velocity) that mass and momentum
     balance give, whatever the populations entering through the plane hold."""
-    rng = np.random.default_rng(31)
+    rng = np.random.default_rng(31 + tag)
     tau = 0.74
     for _ in range(4):
-        rho, U = 1.0 + 0.02 * rng.standard_normal(), np.array([0.03, 0.01, -0.02])
-        o = _node(q, tau=tau, bc_velocity=U)
-        f, g = _open_node_input(q, oracle.TAG_VIN, rng, rho, U)
-        fo, _ = o.collide_node(oracle.TAG_VIN, f)
-        assert np.abs(fo - (oracle.equilibrium(q, rho, U) + (1 - 1 / tau) * g)).max() < 1e-15
-        rho_out, ux = 1.0 + 0.02 * rng.standard_normal(), 0.04 * rng.standard_normal()
-        o = _node(q, tau=tau, bc_density=rho_out)
-        f, g = _open_node_input(q, oracle.TAG_POUT, rng, rho_out, [ux, 0.0, 0.0])
-        fo, _ = o.collide_node(oracle.TAG_POUT, f)
-        assert np.abs(fo - (oracle.equilibrium(q, rho_out, [ux, 0, 0]) + (1 - 1 / tau) * g)).max() < 1e-15
+        rho = 1.0 + 0.02 * rng.standard_normal()
+        if tag in (oracle.TAG_VIN, oracle.TAG_VOUT):
+            u = np.array([0.03, 0.01, -0.02]) * rng.uniform(0.5, 1.5)
+            o = _node(q, tau=tau, bc_velocity=u)
+        else:
+            u = np.array([0.04 * rng.standard_normal(), 0.0, 0.0])
+            o = _node(q, tau=tau, bc_density=(rho, rho))
+        f, g = _open_node_input(q, tag, rng, rho, u)
+        fo, _ = o.collide_node(tag, f)
+        assert np.abs(fo - (oracle.equilibrium(q, rho, u) + (1 - 1 / tau) * g)).max() < 1e-15
 
 
-def _open_channel_tags(nx, ny, nz, walls):
+def _open_channel_tags(nx, ny, nz, walls, low=oracle.TAG_VIN, high=oracle.TAG_POUT):
     t = inputs.channel_tags(nx, ny, nz, fluid_tag=oracle.TAG_TRT) if walls else \
         inputs.all_fluid(nx, ny, nz, oracle.TAG_TRT)
-    t[:, :, 0] = np.where(t[:, :, 0] == oracle.TAG_TRT, oracle.TAG_VIN, t[:, :, 0])
-    t[:, :, -1] = np.where(t[:, :, -1] == oracle.TAG_TRT, oracle.TAG_POUT, t[:, :, -1])
+    t[:, :, 0] = np.where(t[:, :, 0] == oracle.TAG_TRT, low, t[:, :, 0])
+    t[:, :, -1] = np.where(t[:, :, -1] == oracle.TAG_TRT, high, t[:, :, -1])
     return t
 
 
-def test_open_boundaries_keep_uniform_flow():
-    """Uniform flow through an open periodic-in-y,z duct with inlet velocity U and
-    outlet density 1 is a fixed point of the scheme."""
+@pytest.mark.parametrize("pair", [(oracle.TAG_VIN, oracle.TAG_POUT), (oracle.TAG_PIN, oracle.TAG_VOUT),
+                                  (oracle.TAG_VIN, oracle.TAG_VOUT), (oracle.TAG_PIN, oracle.TAG_POUT)])
+def test_open_boundaries_keep_uniform_flow(pair):
+    """Uniform flow at density 1 through an open periodic-in-y,z duct is a fixed
+    point for every pairing of inlet and outlet conditions."""
     nx, ny, nz, U = 12, 3, 4, np.array([0.05, 0.0, 0.0])
-    tags = _open_channel_tags(nx, ny, nz, walls=False)
-    o = oracle.Oracle(nx, ny, nz, q=19, tau=0.7, tags=tags, bc_velocity=U, bc_density=1.0)
+    tags = _open_channel_tags(nx, ny, nz, walls=False, low=pair[0], high=pair[1])
+    o = oracle.Oracle(nx, ny, nz, q=19, tau=0.7, tags=tags, bc_velocity=U, bc_density=(1.0, 1.0))
     u0 = np.zeros((3, nz, ny, nx))
     u0[0] = U[0]
     o.init_equilibrium(None, u0)
@@ -537,20 +543,24 @@ def test_open_boundaries_keep_uniform_flow():
     assert np.abs(o.f[:, inner] - f0[:, inner]).max() < 1e-15
 
 
-def test_open_channel_reaches_poiseuille():
+def _channel_state(pair, nx, nz, tau, steps, U=0.0, rho_in=1.0, rho_out=1.0):
+    tags = _open_channel_tags(nx, 1, nz, walls=True, low=pair[0], high=pair[1])
+    o = oracle.Oracle(nx, 1, nz, q=19, tau=tau, tags=tags, bc_velocity=(U, 0, 0), bc_density=(rho_in, rho_out))
+    u0 = np.zeros((3, nz, 1, nx))
+    u0[0] = U * (tags != 0)
+    o.init_equilibrium(None, u0)
+    o.run(steps)
+    return o.fields()
+
+
+def test_open_channel_velocity_inlet_reaches_poiseuille():
     """Velocity inlet (uniform U) and pressure outlet (rho = 1) between resting walls,
     TRT with Lambda = 3/16: far from the inlet the flow is the Poiseuille profile
     whose pressure gradient is 12 nu rho U_m / H^2 (c_s^2 drho/dx), the mass flux is
     the same through every interior plane, and the profile is the parabola."""
-    nx, ny, nz, U, tau = 96, 1, 18, 0.01, 0.8
+    nx, nz, U, tau = 96, 18, 0.01, 0.8
     H = nz - 2
-    tags = _open_channel_tags(nx, ny, nz, walls=True)
-    o = oracle.Oracle(nx, ny, nz, q=19, tau=tau, tags=tags, bc_velocity=(U, 0, 0), bc_density=1.0)
-    u0 = np.zeros((3, nz, ny, nx))
-    u0[0] = U * (tags != 0)
-    o.init_equilibrium(None, u0)
-    o.run(20000)
-    rho, u = o.fields()
+    rho, u = _channel_state((oracle.TAG_VIN, oracle.TAG_POUT), nx, nz, tau, 20000, U=U)
     flux = (rho * u[0])[1:-1, 0, 1:-1].sum(0)
     assert np.abs(flux / flux.mean() - 1).max() < 1e-3
     nu = (tau - 0.5) / 3.0
@@ -562,3 +572,26 @@ def test_open_channel_reaches_poiseuille():
     z = np.arange(1, nz - 1) - 0.5
     prof = u[0, 1:-1, 0, 60] * rho[1:-1, 0, 60]
     assert np.abs(prof - 6.0 * Um * z * (H - z) / H ** 2).max() < 1e-2 * 1.5 * Um
+
+
+def test_open_channel_pressure_driven_flow_rate():
+    """Pressure inlet and outlet (rho 1.001 and 0.999): the steady flux matches the
+    Poiseuille flow rate H^3 |dp/dx| / (12 nu) of the imposed pressure gradient
+    (dp = c_s^2 drho over the nx - 1 spacings between the boundary planes)."""
+    nx, nz, tau = 64, 18, 0.8
+    H, nu = nz - 2, (0.8 - 0.5) / 3.0
+    rho, u = _channel_state((oracle.TAG_PIN, oracle.TAG_POUT), nx, nz, tau, 15000, rho_in=1.001, rho_out=0.999)
+    flux = (rho * u[0])[1:-1, 0, 1:-1].sum(0)
+    assert np.abs(flux / flux.mean() - 1).max() < 1e-3
+    dpdx = (0.999 - 1.001) / 3.0 / (nx - 1)
+    assert abs(flux.mean() / (H ** 3 * -dpdx / (12 * nu)) - 1.0) < 2e-2
+
+
+def test_open_channel_velocity_boundaries_conserve_mass():
+    """Velocity inlet and velocity outlet with the same U: the mass in the domain
+    stays constant and the steady flux is rho U H through every plane."""
+    nx, nz, U, tau = 48, 18, 0.01, 0.8
+    H = nz - 2
+    rho, u = _channel_state((oracle.TAG_VIN, oracle.TAG_VOUT), nx, nz, tau, 12000, U=U)
+    flux = (rho * u[0])[1:-1, 0, 1:-1].sum(0)
+    assert np.abs(flux / (rho[1:-1, 0, 1:-1].mean(0) * U * H) - 1).max() < 5e-3
