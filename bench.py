@@ -35,7 +35,7 @@ WORKLOADS = {
     "porous400_d3q19_trt": "D3Q19 TRT(3/16) body-force porous 400^3, phi=0.20, corr. length 8",
     "tgv32_d3q19_bgk": "D3Q19 BGK Taylor-Green 32^3, u0=0.04, Re=100 (cache-resident)",
     "porous480_open_d3q19_trt": "D3Q19 TRT(3/16) porous 400^3 rock between 40-plane buffers, regularized "
-                                "velocity inlet / pressure outlet (480x400x400)",
+                                "pressure inlet / pressure outlet (480x400x400)",
     "closure_tgv128_d3q27": "learned closure: D3Q27 TGV Re=1600, fine 512^3 -> coarse 128^3, MLP vs Smagorinsky vs BGK",
 }
 
@@ -80,16 +80,16 @@ def build_workload(name):
         return tags, kw, None, None, {"cells": n ** 3, "porosity": 0.2, "seed": 42}
     if name == "porous480_open_d3q19_trt":
         # the paper's Berea layout (Sec. 3.3): 40 fluid planes upstream, the
-        # 400^3 rock, 40 downstream; regularized velocity inlet at x = 0 and
-        # pressure outlet at x = nx-1; periodic in y and z
+        # 400^3 rock, 40 downstream; regularized pressure boundaries at x = 0
+        # (rho 1.006) and x = nx-1 (rho 1); periodic in y and z
         n, buf = 400, 40
         tags = np.full((n, n, n + 2 * buf), inputs.TAG_TRT, dtype=np.uint8)
         tags[:, :, buf:buf + n] = inputs.porous_tags(n, porosity=0.20, ell=8.0, seed=42)
-        tags[:, :, 0] = inputs.TAG_VIN
+        tags[:, :, 0] = inputs.TAG_PIN
         tags[:, :, -1] = inputs.TAG_POUT
-        kw = dict(q=19, tau=1.0, trt_lambda=3.0 / 16.0, bc_velocity=(5e-6, 0.0, 0.0), bc_density=1.0)
+        kw = dict(q=19, tau=1.0, trt_lambda=3.0 / 16.0, bc_density=(1.006, 1.0))
         return tags, kw, None, None, {"cells": tags.size, "porosity": 0.2, "seed": 42, "buffer": buf,
-                                      "rock": n, "inlet_u": 5e-6}
+                                      "rock": n, "rho_in": 1.006, "rho_out": 1.0}
     if name == "tgv32_d3q19_bgk":
         n, u0 = 32, 0.04
         rho, u = inputs.tgv3d_fields(n, u0)
@@ -102,7 +102,7 @@ def build_workload(name):
 def alg_bytes_per_launch(tags, q, prec_bytes):
     """Algorithmic HBM bytes of one collide-stream launch: every fluid node reads
     and writes its Q populations once; every node's tag byte is read once."""
-    fluid = int(np.isin(tags, (1, 2, 3, 4, 5, 6, 7)).sum())
+    fluid = int(np.isin(tags, (1, 2, 3, 4, 5, 6, 7, 8, 9)).sum())
     return fluid * 2 * q * prec_bytes + tags.size, fluid
 
 
@@ -289,7 +289,7 @@ def main():
             ux_mean = r["series"][-1]["velocity_sum"][0] / tags.size
             k_lu = nu * ux_mean / F
             derived[pn] = {"permeability_lu": k_lu, "permeability_mD": k_lu * (5.345e-6) ** 2 / 9.869233e-16,
-                           "porosity": float(np.isin(tags, (1, 2, 3, 4, 5, 6, 7)).mean()),
+                           "porosity": float(np.isin(tags, (1, 2, 3, 4, 5, 6, 7, 8, 9)).mean()),
                            "steps_total": args.warmup + args.steps,
                            "k_series_lu": [nu * m["velocity_sum"][0] / tags.size / F for m in r["series"][::20]]}
         from paper_2506_09242_amd import inputs as _inp
@@ -301,7 +301,7 @@ def main():
         # (mean fluid density of the plane before the rock - of the plane after it)
         nu = (kw["tau"] - 0.5) / 3.0
         buf, n = wl_cfg["buffer"], wl_cfg["rock"]
-        fl = np.isin(tags, (1, 2, 3, 4, 5, 6, 7))
+        fl = np.isin(tags, (1, 2, 3, 4, 5, 6, 7, 8, 9))
         for pn, r in results.items():
             ux = r["u"][0]
             u_mean = float(ux[:, :, buf:buf + n].mean())

@@ -83,23 +83,28 @@ enum {
                               by its second-order Hermite projection before
                               relaxing (the regularized family of the paper's
                               robust RR model, Sec. 3.1-3.2)                  */
-    LBM_TAG_VEL_IN = 6,    /* regularized velocity inlet, only on the x = 0 plane:
+    LBM_TAG_VEL_IN = 6,    /* regularized velocity boundary on the x = 0 plane:
                               imposes bc_velocity (Sec. 3.3 open boundaries)  */
-    LBM_TAG_PRES_OUT = 7,  /* regularized pressure outlet, only on the x = nx-1
-                              plane: imposes bc_density, zero tangential velocity */
+    LBM_TAG_PRES_OUT = 7,  /* regularized pressure boundary on the x = nx-1 plane:
+                              imposes bc_density[1], zero tangential velocity */
+    LBM_TAG_PRES_IN = 8,   /* regularized pressure boundary on the x = 0 plane:
+                              imposes bc_density[0], zero tangential velocity */
+    LBM_TAG_VEL_OUT = 9,   /* regularized velocity boundary on the x = nx-1 plane:
+                              imposes bc_velocity                             */
     LBM_TAG_WALL0 = 16     /* 16..31: moving wall, velocity wall_velocity[tag-16] */
 };
-/* Open boundaries (LBM_TAG_VEL_IN, LBM_TAG_PRES_OUT; the regularized
- * conditions of Latt et al. 2008 the paper uses for the Berea runs, Sec. 3.3).
- * The lattice stays periodic in x; at an inlet node the populations with
- * c_x = +1 (at an outlet those with c_x = -1) are rebuilt each step from the
- * imposed velocity (density from mass and x-momentum balance over the known
- * populations) or the imposed density (x velocity likewise, y and z velocity
- * zero), each as equilibrium plus its opposite population's non-equilibrium
- * part; the node is then regularized (second-order Hermite projection) and
- * relaxed with tau.  The body force is not applied on these nodes.  Reads and
- * reductions report their stored populations, whose entering ones are those
- * streamed across the periodic x wrap. */
+/* Open boundaries (tags 6..9; the regularized conditions of Latt et al. 2008
+ * the paper uses for the Berea runs, Sec. 3.3, with pressure or velocity
+ * imposed at either end).  The lattice stays periodic in x; on the x = 0
+ * plane the populations with c_x = +1 (on x = nx-1 those with c_x = -1) are
+ * rebuilt each step from the imposed velocity (density from mass and
+ * x-momentum balance over the known populations) or the imposed density
+ * (x velocity likewise, y and z velocity zero), each as equilibrium plus its
+ * opposite population's non-equilibrium part; the node is then regularized
+ * (second-order Hermite projection) and relaxed with tau.  The body force is
+ * not applied on these nodes.  Reads and reductions report their stored
+ * populations, whose entering ones are those streamed across the periodic x
+ * wrap. */
 
 typedef struct {
     int32_t nx, ny, nz;    /* lattice size, each >= 1, nx*ny*nz < 2^31          */
@@ -112,8 +117,9 @@ typedef struct {
     double smag_cs;        /* Smagorinsky constant, >= 0                         */
     double force[3];       /* uniform body-force density (Guo), |F| < 0.3       */
     double wall_velocity[16][3]; /* velocity of wall tags 16..31, |u| < 0.3     */
-    double bc_velocity[3]; /* velocity imposed on LBM_TAG_VEL_IN nodes, |u| < 0.3 */
-    double bc_density;     /* density imposed on LBM_TAG_PRES_OUT nodes (> 0)    */
+    double bc_velocity[3]; /* velocity of velocity-boundary nodes (6, 9), |u| < 0.3 */
+    double bc_density[2];  /* density of pressure-boundary nodes (> 0): [0] on
+                              x = 0 (tag 8), [1] on x = nx-1 (tag 7)          */
 } lbm_config;
 
 /* FP64 domain reductions of the natural state at time `step`, over fluid nodes. */

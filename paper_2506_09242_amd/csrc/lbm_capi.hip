@@ -114,7 +114,7 @@ size_t elem_bytes(int prec) { return prec == LBM_F64 ? 8 : (prec == LBM_F32 ? 4 
 // (the blocked layout of pop_base).
 long long pop_elems(long long ncell, int q) { return (ncell + kBlockNodes - 1) / kBlockNodes * kBlockNodes * q; }
 
-bool known_tag(int t) { return (t >= 0 && t <= 7) || (t >= 16 && t <= 31); }
+bool known_tag(int t) { return (t >= 0 && t <= 9) || (t >= 16 && t <= 31); }
 
 // Storage sectors of 64 bytes hold 8 (FP64), 16 (FP32) or 32 (FP16) nodes.
 int sector_log2(int prec) { return prec == LBM_F64 ? 3 : (prec == LBM_F32 ? 4 : 5); }
@@ -127,7 +127,7 @@ long long count_fillers(const uint8_t *tags, long long N, int sector_log2) {
     for (long long a = 0; a < N; a += g) {
         const long long b = a + g < N ? a + g : N;
         long long fl = 0;
-        for (long long k = a; k < b; ++k) fl += (tags[k] >= 1 && tags[k] <= 7);
+        for (long long k = a; k < b; ++k) fl += (tags[k] >= 1 && tags[k] <= 9);
         if (fl) count += (b - a) - fl;
     }
     return count;
@@ -208,7 +208,8 @@ StepParams step_params(const lbm_lattice *L) {
     p.nu0 = (c.tau - 0.5) / 3.0;
     for (int a = 0; a < 3; ++a) p.force[a] = c.force[a];
     for (int a = 0; a < 3; ++a) p.bc_u[a] = c.bc_velocity[a];
-    p.bc_rho = c.bc_density;
+    p.bc_rho[0] = c.bc_density[0];
+    p.bc_rho[1] = c.bc_density[1];
     p.mlp = L->mlp;
     return p;
 }
@@ -383,22 +384,23 @@ static lbm_status create_impl(const lbm_config *cfg, const uint8_t *tags_host, v
     for (long long n = 0; n < N; ++n) {
         const int t = tags_host[n];
         if (!known_tag(t)) return set_err(LBM_EINVAL, "unknown tag value %d at node %lld", t, n);
-        if (t == LBM_TAG_VEL_IN && n % cfg->nx != 0)
-            return set_err(LBM_EINVAL, "velocity-inlet tag off the x = 0 plane at node %lld", n);
-        if (t == LBM_TAG_PRES_OUT && n % cfg->nx != cfg->nx - 1)
-            return set_err(LBM_EINVAL, "pressure-outlet tag off the x = nx-1 plane at node %lld", n);
+        if ((t == LBM_TAG_VEL_IN || t == LBM_TAG_PRES_IN) && n % cfg->nx != 0)
+            return set_err(LBM_EINVAL, "open-boundary tag %d off the x = 0 plane at node %lld", t, n);
+        if ((t == LBM_TAG_PRES_OUT || t == LBM_TAG_VEL_OUT) && n % cfg->nx != cfg->nx - 1)
+            return set_err(LBM_EINVAL, "open-boundary tag %d off the x = nx-1 plane at node %lld", t, n);
         hist[t]++;
     }
-    if ((hist[LBM_TAG_VEL_IN] || hist[LBM_TAG_PRES_OUT]) && cfg->nx < 2)
-        return set_err(LBM_EINVAL, "open boundaries need nx >= 2");
-    if (hist[LBM_TAG_VEL_IN]) {
+    const long long n_open = hist[LBM_TAG_VEL_IN] + hist[LBM_TAG_PRES_OUT] + hist[LBM_TAG_PRES_IN] + hist[LBM_TAG_VEL_OUT];
+    if (n_open && cfg->nx < 2) return set_err(LBM_EINVAL, "open boundaries need nx >= 2");
+    if (hist[LBM_TAG_VEL_IN] || hist[LBM_TAG_VEL_OUT]) {
         const double *u = cfg->bc_velocity;
         if (!(std::sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) < 0.3))
             return set_err(LBM_EINVAL, "|bc_velocity| must be < 0.3");
     }
-    if (hist[LBM_TAG_PRES_OUT] && !(cfg->bc_density > 0.0)) return set_err(LBM_EINVAL, "bc_density must be > 0");
+    if (hist[LBM_TAG_PRES_IN] && !(cfg->bc_density[0] > 0.0)) return set_err(LBM_EINVAL, "bc_density[0] must be > 0");
+    if (hist[LBM_TAG_PRES_OUT] && !(cfg->bc_density[1] > 0.0)) return set_err(LBM_EINVAL, "bc_density[1] must be > 0");
     long long nf = 0;
-    for (int t = 1; t <= 7; ++t) nf += hist[t];
+    for (int t = 1; t <= 9; ++t) nf += hist[t];
     if (nf == 0) return set_err(LBM_EINVAL, "no fluid node");
     int need = 0;
     if (hist[LBM_TAG_BGK]) need |= MS_BGK;
@@ -406,7 +408,7 @@ static lbm_status create_impl(const lbm_config *cfg, const uint8_t *tags_host, v
     if (hist[LBM_TAG_BGK_SMAG]) need |= MS_SMAG;
     if (hist[LBM_TAG_BGK_MLP]) need |= MS_MLP;
     if (hist[LBM_TAG_REG]) need |= MS_REG;
-    if (hist[LBM_TAG_VEL_IN] || hist[LBM_TAG_PRES_OUT]) need |= MS_OPEN;
+    if (n_open) need |= MS_OPEN;
     int ms = -1;
     for (int k = 0; k < kNumModelSets; ++k)
         if ((kModelSets[k] & need) == need) {
@@ -415,7 +417,7 @@ static lbm_status create_impl(const lbm_config *cfg, const uint8_t *tags_host, v
         }
     if (ms < 0) return set_err(LBM_EUNSUPPORTED, "no compiled model set covers the tags");
     int n_models = 0, only = LBM_TAG_BGK;
-    for (int t = 1; t <= 7; ++t)
+    for (int t = 1; t <= 9; ++t)
         if (hist[t]) {
             n_models++;
             only = t;

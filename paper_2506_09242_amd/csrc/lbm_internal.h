@@ -22,7 +22,7 @@ enum ModelSet : int {
     MS_SMAG = 4,
     MS_MLP = 8,
     MS_REG = 16,
-    MS_OPEN = 32,  // regularized velocity inlet / pressure outlet nodes
+    MS_OPEN = 32,  // regularized velocity / pressure boundary nodes on the x planes
 };
 
 // Compiled model-set variants, smallest first.  The host picks the first one
@@ -81,8 +81,8 @@ struct StepParams {
     double smag_c;            // 18 sqrt(2) Cs^2 (implicit Smagorinsky)
     double nu0;               // (tau - 1/2) / 3
     double force[3];
-    double bc_u[3];           // velocity imposed on inlet nodes
-    double bc_rho;            // density imposed on outlet nodes
+    double bc_u[3];           // velocity imposed on velocity-boundary nodes
+    double bc_rho[2];         // density imposed on pressure-boundary nodes (x = 0, x = nx-1)
     MlpDev mlp;
 };
 

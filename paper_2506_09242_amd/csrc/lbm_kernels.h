@@ -84,18 +84,20 @@ __device__ __forceinline__ void node_reduce(const C (&h)[Q], bool live, const St
 
 // Regularized open boundary on an x plane (the conditions of Latt et al. 2008
 // the paper uses for the Berea runs, Sec. 3.3), shifted form: f_i = h_i + w_i rho0.
-// Inlet (x = 0): populations with c_x = +1 enter from outside; the velocity is
-// imposed and the density follows from mass and x-momentum over the known ones,
-//   rho (1 - u_x) = sum_{c_x=0} f + 2 sum_{c_x=-1} f = s0 + 2 s- + rho0
-// (the weights of c_x = 0 plus twice those of c_x = -1 sum to 1).  Outlet
-// (x = nx-1): populations with c_x = -1 are unknown, the density is imposed,
-// u_y = u_z = 0 and u_x = (s0 + 2 s+ + rho0) / rho - 1.  Each unknown population
+// On the x = 0 plane the populations with c_x = +1 come from outside, on
+// x = nx-1 those with c_x = -1.  Mass and x-momentum over the known populations
+// give, with s = -1 on x = 0 and s = +1 on x = nx-1,
+//   rho (1 + s u_x) = sum_{c_x=0} f + 2 sum_{c_x=s} f = s0 + 2 s_s + rho0 = K
+// (the weights of c_x = 0 plus twice those of c_x = s sum to 1): a velocity
+// boundary (u imposed) has rho = K / (1 + s u_x), a pressure boundary (rho
+// imposed, u_y = u_z = 0) has u_x = s (K / rho - 1).  Each unknown population
 // is equilibrium plus its opposite's non-equilibrium part; the node is then
 // regularized (Hermite projection of its momentum flux) and relaxed with omega.
 // No body force on these nodes.
 template <int Q, typename C>
 __device__ __forceinline__ void open_boundary(const C (&h)[Q], int tag, const StepParams &p, C (&hs)[Q]) {
-    const bool inlet = tag == LBM_TAG_VEL_IN;
+    const bool low = tag == LBM_TAG_VEL_IN || tag == LBM_TAG_PRES_IN;  // the x = 0 plane
+    const bool vel = tag == LBM_TAG_VEL_IN || tag == LBM_TAG_VEL_OUT;  // velocity imposed
     C s0 = C(0), sp = C(0), sm = C(0);
     sfor<Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
@@ -105,15 +107,17 @@ __device__ __forceinline__ void open_boundary(const C (&h)[Q], int tag, const St
         if constexpr (Vi::x < 0) sm += h[i];
     });
     const C rho0 = (C)p.rho0;
+    const C sg = low ? C(-1) : C(1);
+    const C K = s0 + C(2) * (low ? sm : sp) + rho0;
     C rb, ux, uy, uz;
-    if (inlet) {
+    if (vel) {
         ux = (C)p.bc_u[0];
         uy = (C)p.bc_u[1];
         uz = (C)p.bc_u[2];
-        rb = (s0 + C(2) * sm + rho0) / (C(1) - ux);
+        rb = K / (C(1) + sg * ux);
     } else {
-        rb = (C)p.bc_rho;
-        ux = (s0 + C(2) * sp + rho0) / rb - C(1);
+        rb = (C)p.bc_rho[low ? 0 : 1];
+        ux = sg * (K / rb - C(1));
         uy = C(0);
         uz = C(0);
     }
@@ -139,7 +143,7 @@ __device__ __forceinline__ void open_boundary(const C (&h)[Q], int tag, const St
             constexpr int o = Vi::opp;
             C ne = h[i] - he[i];
             if constexpr (Vi::x != 0) {
-                const bool unknown = inlet ? (Vi::x > 0) : (Vi::x < 0);
+                const bool unknown = low ? (Vi::x > 0) : (Vi::x < 0);
                 if (unknown) ne = h[o] - he[o];
             }
             if constexpr (Vi::x != 0) pxx += ne;
@@ -309,7 +313,7 @@ __device__ __forceinline__ void collide_node(const C (&h)[Q], int tag, bool live
     });
 
     if constexpr ((MS & MS_OPEN) != 0) {
-        if (tag == LBM_TAG_VEL_IN || tag == LBM_TAG_PRES_OUT) open_boundary<Q, C>(h, tag, p, hs);
+        if (tag >= LBM_TAG_VEL_IN && tag <= LBM_TAG_VEL_OUT) open_boundary<Q, C>(h, tag, p, hs);
     }
 }
 

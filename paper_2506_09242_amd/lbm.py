@@ -21,7 +21,8 @@ LIB_PATH = os.path.join(_HERE, "liblbm_hip.so")
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EHIP, LBM_EUNSTABLE, LBM_EUNSUPPORTED, LBM_ESTATE = 0, -1, -2, -3, -4, -5, -6
 LBM_F64, LBM_F32, LBM_F16S = 0, 1, 2
-TAG_SOLID, TAG_BGK, TAG_TRT, TAG_SMAG, TAG_MLP, TAG_REG, TAG_VIN, TAG_POUT, TAG_WALL0 = 0, 1, 2, 3, 4, 5, 6, 7, 16
+TAG_SOLID, TAG_BGK, TAG_TRT, TAG_SMAG, TAG_MLP, TAG_REG, TAG_WALL0 = 0, 1, 2, 3, 4, 5, 16
+TAG_VIN, TAG_POUT, TAG_PIN, TAG_VOUT = 6, 7, 8, 9  # open boundaries on the x planes
 MLP_NPARAMS = 1359
 PREC_NAMES = {"f64": LBM_F64, "f32": LBM_F32, "f16s": LBM_F16S}
 PREC_BYTES = {LBM_F64: 8, LBM_F32: 4, LBM_F16S: 2}
@@ -32,7 +33,7 @@ class LbmConfig(C.Structure):
                 ("prec", C.c_int32), ("flags", C.c_int32), ("rho0", C.c_double), ("tau", C.c_double),
                 ("trt_lambda", C.c_double), ("smag_cs", C.c_double), ("force", C.c_double * 3),
                 ("wall_velocity", (C.c_double * 3) * 16), ("bc_velocity", C.c_double * 3),
-                ("bc_density", C.c_double)]
+                ("bc_density", C.c_double * 2)]
 
 
 class LbmMoments(C.Structure):
@@ -120,7 +121,7 @@ def _dev(t):
 
 def make_config(nx, ny, nz, q=19, prec=LBM_F64, tau=0.8, rho0=1.0, trt_lambda=3.0 / 16.0, smag_cs=0.0,
                 force=(0.0, 0.0, 0.0), wall_velocity: Optional[Sequence] = None, bc_velocity=(0.0, 0.0, 0.0),
-                bc_density=1.0) -> LbmConfig:
+                bc_density=(1.0, 1.0)) -> LbmConfig:
     if isinstance(prec, str):
         prec = PREC_NAMES[prec]
     c = LbmConfig()
@@ -134,7 +135,7 @@ def make_config(nx, ny, nz, q=19, prec=LBM_F64, tau=0.8, rho0=1.0, trt_lambda=3.
                 c.wall_velocity[k][a] = v[a]
     for a in range(3):
         c.bc_velocity[a] = bc_velocity[a]
-    c.bc_density = bc_density
+    c.bc_density[0], c.bc_density[1] = bc_density
     return c
 
 
@@ -186,7 +187,7 @@ class Lattice:
 
     def __init__(self, tags: np.ndarray, q=19, prec=LBM_F64, tau=0.8, rho0=1.0, trt_lambda=3.0 / 16.0,
                  smag_cs=0.0, force=(0.0, 0.0, 0.0), wall_velocity=None, stream=None, torch_buffer=False,
-                 bc_velocity=(0.0, 0.0, 0.0), bc_density=1.0):
+                 bc_velocity=(0.0, 0.0, 0.0), bc_density=(1.0, 1.0)):
         tags = np.ascontiguousarray(tags, dtype=np.uint8)
         assert tags.ndim == 3
         nz, ny, nx = tags.shape

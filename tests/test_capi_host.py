@@ -84,9 +84,9 @@ def test_create_rejects_bad_config(field, value, needle):
 def test_create_rejects_bad_tags_and_fast_flows():
     cfg = lbm.make_config(4, 4, 4)
     t = inputs.all_fluid(4, 4, 4)
-    t[1, 2, 3] = 9
+    t[1, 2, 3] = 12
     rc, _ = _create(cfg, t)
-    assert rc == lbm.LBM_EINVAL and "unknown tag value 9" in lbm.lbm_last_error()
+    assert rc == lbm.LBM_EINVAL and "unknown tag value 12" in lbm.lbm_last_error()
     # open boundaries: inlet only on x = 0, outlet only on x = nx-1, sane values
     t = inputs.all_fluid(4, 4, 4)
     t[0, 0, 1] = lbm.TAG_VIN
@@ -102,8 +102,16 @@ def test_create_rejects_bad_tags_and_fast_flows():
     assert rc == lbm.LBM_EINVAL and "bc_velocity" in lbm.lbm_last_error()
     t = inputs.all_fluid(4, 4, 4)
     t[:, :, -1] = lbm.TAG_POUT
-    rc, _ = _create(lbm.make_config(4, 4, 4, bc_density=0.0), t)
-    assert rc == lbm.LBM_EINVAL and "bc_density" in lbm.lbm_last_error()
+    rc, _ = _create(lbm.make_config(4, 4, 4, bc_density=(1.0, 0.0)), t)
+    assert rc == lbm.LBM_EINVAL and "bc_density[1]" in lbm.lbm_last_error()
+    t = inputs.all_fluid(4, 4, 4)
+    t[:, :, 0] = lbm.TAG_PIN
+    rc, _ = _create(lbm.make_config(4, 4, 4, bc_density=(-1.0, 1.0)), t)
+    assert rc == lbm.LBM_EINVAL and "bc_density[0]" in lbm.lbm_last_error()
+    t = inputs.all_fluid(4, 4, 4)
+    t[0, 1, 2] = lbm.TAG_VOUT
+    rc, _ = _create(cfg, t)
+    assert rc == lbm.LBM_EINVAL and "x = nx-1 plane" in lbm.lbm_last_error()
     rc, _ = _create(cfg, np.zeros((4, 4, 4), np.uint8))
     assert rc == lbm.LBM_EINVAL and "no fluid" in lbm.lbm_last_error()
     cfg = lbm.make_config(4, 4, 4, force=(0.4, 0, 0))

@@ -131,20 +131,24 @@ def test_regularized_cavity_and_force_fp64(q, steps):
     assert err <= TOL
 
 
-def _open_channel(nx, ny, nz, bulk):
+def _open_channel(nx, ny, nz, bulk, low=inputs.TAG_VIN, high=inputs.TAG_POUT):
     t = inputs.channel_tags(nx, ny, nz, fluid_tag=bulk)
-    t[:, :, 0] = np.where(t[:, :, 0] == bulk, inputs.TAG_VIN, t[:, :, 0])
-    t[:, :, -1] = np.where(t[:, :, -1] == bulk, inputs.TAG_POUT, t[:, :, -1])
+    t[:, :, 0] = np.where(t[:, :, 0] == bulk, low, t[:, :, 0])
+    t[:, :, -1] = np.where(t[:, :, -1] == bulk, high, t[:, :, -1])
     return t
 
 
-@pytest.mark.parametrize("q,steps", [(19, 301), (27, 120)])
-def test_open_boundaries_channel_fp64(q, steps):
-    """Regularized velocity inlet and pressure outlet between resting walls (TRT
-    bulk, the trt+open kernel), developing channel flow."""
-    tags = _open_channel(40, 5, 12, inputs.TAG_TRT)
+@pytest.mark.parametrize("q,steps,pair", [(19, 301, (inputs.TAG_VIN, inputs.TAG_POUT)),
+                                          (27, 120, (inputs.TAG_VIN, inputs.TAG_POUT)),
+                                          (19, 201, (inputs.TAG_PIN, inputs.TAG_VOUT)),
+                                          (27, 77, (inputs.TAG_PIN, inputs.TAG_POUT))])
+def test_open_boundaries_channel_fp64(q, steps, pair):
+    """Regularized velocity / pressure boundaries on both x planes between resting
+    walls (TRT bulk, the trt+open kernel), developing channel flow."""
+    tags = _open_channel(40, 5, 12, inputs.TAG_TRT, *pair)
     rho, u = inputs.random_fields(40, 5, 12, seed=41, du=0.0)
-    o, L = make_pair(tags, q=q, tau=0.8, bc_velocity=(0.04, 0.0, 0.005), bc_density=1.01, rho=rho, u=u)
+    o, L = make_pair(tags, q=q, tau=0.8, bc_velocity=(0.04, 0.0, 0.005), bc_density=(1.004, 0.998),
+                     rho=rho, u=u)
     assert L.variant == f"D3Q{q}/f64/trt+open/tagged"
     L.step(steps)
     o.run(steps)
@@ -161,7 +165,7 @@ def test_open_boundaries_with_every_model_fp64():
     tags[3:6, 1:3, 15] = inputs.TAG_SMAG
     tags[3:6, 1:3, 20] = inputs.TAG_BGK
     o, L = make_pair(tags, q=19, tau=0.7, smag_cs=0.12, force=(2e-6, 0, 0), bc_velocity=(0.03, 0, 0),
-                     bc_density=1.0, wall_velocity=[(0.02, 0, 0)])
+                     bc_density=(1.0, 1.0), wall_velocity=[(0.02, 0, 0)])
     assert L.variant.endswith("/all/tagged")
     L.step(151)
     o.run(151)

@@ -330,7 +330,7 @@ def test_moments_match_exact_sum_of_fields():
     o.run(3)
     m = o.moments()
     r, v = o.fields()
-    fl = (tags >= 1) & (tags <= 7)
+    fl = (tags >= 1) & (tags <= 9)
     uu = (v ** 2).sum(0)
     assert m["n_fluid"] == fl.sum()
     assert abs(m["ke_sum"] - math.fsum((0.5 * uu[fl]).ravel())) <= 2e-16 * m["ke_sum"]
