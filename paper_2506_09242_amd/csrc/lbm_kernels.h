@@ -21,8 +21,10 @@
 // takes slot i at x instead.
 //
 // Node update (Sec. 2.3 push-pull scheme): the Q populations of a node are
-// pulled into registers, the tag selects the collision model (switch over
-// the compiled model set), and the results are pushed back.  Populations are
+// pulled into registers, the tag selects the collision model among the
+// compiled model set (BGK, TRT, BGK with Smagorinsky or the learned eddy
+// viscosity, regularized BGK, regularized open boundaries), and the results
+// are pushed back (slot addresses from pop_base / slot_off).  Populations are
 // stored shifted, h_i = f_i - w_i rho0 (Sec. 3 intro, Skordos' offset
 // stripping), which the collision is written for directly:
 //   drho = sum h_i, rho = rho0 + drho, j = sum c_i h_i, u = (j + F/2) / rho
