@@ -45,7 +45,7 @@ struct lbm_lattice {
     double *d_partials = nullptr;   // [NRED][max_tiles]
     long long max_tiles = 0;
     double *d_stage1 = nullptr;     // [NRED][kFinalizeBlocks]
-    int *d_tile_tag = nullptr;      // [max_tiles] tile classification of the current tiling
+    int *d_tile_tag = nullptr;      // [max_tiles][4] wave classification of the current tiling
     uint32_t *d_mask = nullptr;     // [N] neighbour masks (tagged lattices)
     double *d_series = nullptr;     // [series_cap][NRED]
     long long series_cap = 0;
@@ -290,30 +290,38 @@ __global__ __launch_bounds__(256) void k_finalize2(const double *stage1, int nb,
 // One block per tile: load the tile's tags with a one-node halo (periodic)
 // and report the tag if every one of them is the same fluid tag, else 0.
 __global__ __launch_bounds__(256) void k_tile_classify(StepParams p, int *out) {
-    __shared__ int s_first, s_same;
+    // One block per tile; wave w of the block classifies the 64 nodes that wave
+    // w of the step kernel updates, together with their one-node halo.
     const int L = blockIdx.x;
     const int txl = p.tx_log2;
-    const int TX = 1 << txl, TY = 256 >> txl;
+    const int TX = 1 << txl;
     const int tix = L % p.tiles_x, rem = L / p.tiles_x;
     const int tiy = rem % p.tiles_y, z = rem / p.tiles_y;
-    const int x0 = tix * TX, y0 = tiy * TY;
-    const int WX = TX + 2, WY = TY + 2;
-    if (threadIdx.x == 0) {
-        s_first = p.tags[((long long)z * p.ny + y0) * p.nx + x0];
-        s_same = 1;
+    const int x0 = tix * TX, y0 = tiy * (256 >> txl);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int t = threadIdx.x;
+    const int x = x0 + (t & (TX - 1)), y = y0 + (t >> txl);
+    const bool in = x < p.nx && y < p.ny;
+    const int xc = in ? x : x0 < p.nx ? x0 : 0, yc = in ? y : y0 < p.ny ? y0 : 0;
+    const int first = p.tags[((long long)z * p.ny + yc) * p.nx + xc];
+    // the wave's first in-range node sets the reference tag
+    const unsigned long long act = __ballot(in);
+    const int src = act ? __ffsll((long long)act) - 1 : 0;
+    const int ref = __shfl(first, src, 64);
+    bool same = act != 0ull && is_fluid_tag(ref);
+    if (in) {
+        for (int dz = -1; dz <= 1; ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const int gx = (x + dx + p.nx) % p.nx, gy = (y + dy + p.ny) % p.ny;
+                    const int gz = (z + dz + p.nz) % p.nz;
+                    if (p.tags[((long long)gz * p.ny + gy) * p.nx + gx] != ref) same = false;
+                }
     }
-    __syncthreads();
-    const int first = s_first;
-    bool same = is_fluid_tag(first);
-    for (int k = threadIdx.x; k < WX * WY * 3; k += 256) {
-        const int ax = k % WX, r = k / WX, ay = r % WY, az = r / WY;
-        const int gx = (x0 + ax - 1 + p.nx) % p.nx, gy = (y0 + ay - 1 + p.ny) % p.ny;
-        const int gz = (z + az - 1 + p.nz) % p.nz;
-        if (p.tags[((long long)gz * p.ny + gy) * p.nx + gx] != first) same = false;
-    }
-    if (!same) s_same = 0;
-    __syncthreads();
-    if (threadIdx.x == 0) out[L] = s_same ? first : 0;
+    // a wave is plain when every in-range lane saw only the reference tag
+    const bool all = __ballot(in && !same) == 0ull && same;
+    if (lane == 0) out[(long long)L * 4 + w] = all ? ref : 0;
+    (void)lane;
 }
 
 hipError_t launch_tile_classify(const StepParams &p, int *out, hipStream_t s) {
@@ -505,7 +513,7 @@ static lbm_status create_impl(const lbm_config *cfg, const uint8_t *tags_host, v
         L->d_stage1 = nullptr;
         return bail(set_err(LBM_ENOMEM, "hipMalloc of reduction stage buffer failed"));
     }
-    e = hipMalloc(&L->d_tile_tag, (size_t)max_tiles * sizeof(int));
+    e = hipMalloc(&L->d_tile_tag, (size_t)max_tiles * 4 * sizeof(int));
     if (e != hipSuccess) {
         (void)hipGetLastError();
         L->d_tile_tag = nullptr;

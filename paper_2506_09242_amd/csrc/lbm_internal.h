@@ -59,9 +59,9 @@ struct MlpDev {
 struct StepParams {
     void *pops;               // population array (blocked layout, see pop_base)
     const uint8_t *tags;      // device tags (TAGGED variants)
-    const int *tile_tag;      // per tile: the fluid tag (1..4) when the tile and its
-                              // one-node halo are that one model, else 0 (32-bit
-                              // words so a block reads its entry with a scalar load)
+    const int *tile_tag;      // per tile and wave ([tile][4]): the fluid tag when the
+                              // wave's 64 nodes and their one-node halo are that one
+                              // model, else 0 (32-bit words: one scalar load per wave)
     const uint32_t *mask;     // per-node neighbour mask (TAGGED variants)
     const double *wall_u;     // [16][3] moving-wall velocities (device)
     double *partials;         // [NRED][partial_stride] per-tile reduction partials
@@ -123,7 +123,7 @@ hipError_t launch_scatter(const AuxParams &a, hipStream_t s);
 // Deterministic two-stage sum of the per-tile partials into out[NRED];
 // stage1 holds NRED * kFinalizeBlocks doubles.
 constexpr int kFinalizeBlocks = 256;
-// Classify every tile of the current tiling (see StepParams::tile_tag).
+// Classify every wave of every tile of the current tiling (see StepParams::tile_tag).
 hipError_t launch_tile_classify(const StepParams &p, int *out, hipStream_t s);
 
 hipError_t launch_finalize(const double *partials, long long partial_stride, int n_tiles, double *stage1, double *out,

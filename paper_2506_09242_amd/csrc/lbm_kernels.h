@@ -365,7 +365,8 @@ __global__ __launch_bounds__(256) void k_collide_stream(StepParams p) {
     if constexpr (TAGGED) {
         // block-uniform entry read through the constant address space (scalar load)
         typedef const __attribute__((address_space(4))) int const_int;
-        const int tile_tag = ((const_int *)p.tile_tag)[L];
+        const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        const int tile_tag = ((const_int *)p.tile_tag)[L * 4 + wave];
         if (tile_tag != 0) {
             tag = tile_tag;
         } else {
