@@ -354,16 +354,16 @@ __global__ __launch_bounds__(256) void k_collide_stream(StepParams p) {
     const int zo[3] = {(z == 0 ? nz - 1 : z - 1) * nxy, z * nxy, (z + 1 == nz ? 0 : z + 1) * nxy};
     const int n = zo[1] + yo[1] + xo[1];
 
-    // Node class.  Tiles whose one-node halo is a single fluid model (the
-    // interior of a walled domain) need nothing; the other tiles read each
-    // node's precomputed neighbour mask (block-uniform branch).
+    // Node class.  Waves whose 64 nodes and their one-node halo are a single
+    // fluid model (the interior of a walled domain) need nothing; the other
+    // waves read each node's precomputed neighbour mask (wave-uniform branch).
     S *__restrict__ f = static_cast<S *>(p.pops);
     const long long pb = pop_base<Q>(n);
     int tag = p.uniform_tag;
     uint32_t wall = 0;   // bit i: node x + c_i is not fluid
     bool moving = false; // some neighbour is a moving wall
     if constexpr (TAGGED) {
-        // block-uniform entry read through the constant address space (scalar load)
+        // wave-uniform entry read through the constant address space (scalar load)
         typedef const __attribute__((address_space(4))) int const_int;
         const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
         const int tile_tag = ((const_int *)p.tile_tag)[L * 4 + wave];
