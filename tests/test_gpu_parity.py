@@ -363,3 +363,37 @@ def test_enstrophy_vs_oracle():
     with pytest.raises(lbm.LbmError) as e:
         walled.enstrophy()
     assert e.value.status == lbm.LBM_EUNSUPPORTED
+
+
+# ------------------------------------------- full-size cavity, sampled cells
+def _bench_workload(name):
+    import os
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import bench
+    return bench.build_workload(name)
+
+
+@pytest.mark.parametrize("prec,bound", [(lbm.LBM_F64, TOL), (lbm.LBM_F32, 1e-5)])
+def test_full_size_cavity_sampled_cells(prec, bound):
+    """The benchmark's workload at its full size and launch configuration (the
+    256^3 lid-driven cavity, default tiling) from a random near-rest state, 11
+    steps: sampled cells (all lid-adjacent nodes of four rows, the x-wall
+    columns, and random nodes) match the oracle's populations (FP64 to 1e-12
+    relative; FP32 storage within 1e-5)."""
+    tags, kw, _, _, _ = _bench_workload("cavity256_d3q19_bgk")
+    nz, ny, nx = tags.shape
+    rho, u = inputs.random_fields(nx, ny, nz, seed=77, du=0.01, drho=0.005)
+    o, L = make_pair(tags, prec=prec, rho=rho, u=u, **kw)
+    L.step(11)
+    o.run(11)
+    rng = np.random.default_rng(5)
+    fl = np.flatnonzero(fluid_mask(tags).reshape(-1))
+    lid = [((nz - 2) * ny + y) * nx + x for y in (1, 2, 127, ny - 2) for x in range(1, nx - 1)]
+    xwall = [(z * ny + y) * nx + x for z in (1, 128, nz - 2) for y in range(1, ny - 1) for x in (1, nx - 2)]
+    cells = np.unique(np.concatenate([lid, xwall, rng.choice(fl, 20000, replace=False)]))
+    g = L.read_cells(cells)
+    ref = o.f.reshape(kw["q"], -1)[:, cells].T
+    err = float(np.abs(g / ref - 1.0).max())
+    _print("full cavity", prec, cells.size, err)
+    assert err <= bound
