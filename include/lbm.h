@@ -13,8 +13,10 @@
  *     "Collision-model polymorphism without virtual function calls") and a
  *     kernel specialised on the subset of models actually present
  *     (Sec. 2.3, "GPU kernel size reduction");
- *   - BGK and TRT collisions, the Smagorinsky subgrid closure, standard and
- *     moving-wall half-way bounce-back (Sec. 3 introduction; Sec. 3.2, 3.3);
+ *   - BGK and TRT collisions, the Smagorinsky subgrid closure, regularized
+ *     BGK, standard and moving-wall half-way bounce-back (Sec. 3
+ *     introduction; Sec. 3.2, 3.3), regularized velocity / pressure open
+ *     boundaries on the x planes (Sec. 3.3);
  *   - populations stored with the constant offset w_i rho0 removed
  *     (Sec. 3 introduction, after Skordos), in FP64, FP32 or FP16 storage;
  *   - fused FP64 domain reductions of mass, momentum and kinetic energy
@@ -26,7 +28,8 @@
  *   - Every call returns lbm_status: 0 on success, a negative code on error.
  *     The text of the last error of the calling thread is lbm_last_error().
  *   - Lattice cells are indexed n = (z*ny + y)*nx + x (x fastest).  Every
- *     axis is periodic; walls are explicit non-fluid tags.
+ *     axis is periodic; walls are explicit non-fluid tags and open
+ *     boundaries explicit boundary tags on the x planes.
  *   - Velocities use the canonical order documented at lbm_velocity().
  *   - Pointers named *_host are host memory, borrowed for the duration of the
  *     call only.  Pointers named *_dev are device memory on the lattice's
