@@ -20,6 +20,7 @@ _lib = None
 
 TAG_SOLID, TAG_BGK, TAG_TRT, TAG_SMAG, TAG_MLP, TAG_REG, TAG_WALL0 = 0, 1, 2, 3, 4, 5, 16
 TAG_VIN, TAG_POUT, TAG_PIN, TAG_VOUT = 6, 7, 8, 9  # open boundaries on the x planes
+TAG_RR = 10
 MLP_PARAMS = 1359
 
 
@@ -45,6 +46,8 @@ def lib():
         L.orc_velocity.restype = C.c_int
         L.orc_equilibrium.argtypes = [C.c_int, C.c_double, dp, dp]
         L.orc_equilibrium.restype = None
+        L.orc_equilibrium3.argtypes = [C.c_int, C.c_double, dp, dp]
+        L.orc_equilibrium3.restype = None
         L.orc_collide_node.argtypes = [C.POINTER(OrcConfig), C.c_int, dp, dp, C.POINTER(C.c_double)]
         L.orc_collide_node.restype = C.c_int
         L.orc_init.argtypes = [C.POINTER(OrcConfig), u8, C.c_void_p, C.c_void_p, dp]
@@ -158,6 +161,13 @@ class Oracle:
 def equilibrium(q, rho, u):
     feq = np.zeros(q)
     lib().orc_equilibrium(q, rho, np.ascontiguousarray(u, dtype=np.float64), feq)
+    return feq
+
+
+def equilibrium3(q, rho, u):
+    """Third-order Hermite equilibrium (the recursive regularized model's)."""
+    feq = np.zeros(q)
+    lib().orc_equilibrium3(q, rho, np.ascontiguousarray(u, dtype=np.float64), feq)
     return feq
 
 

@@ -28,6 +28,14 @@
  *     momentum balance) or the imposed density (normal velocity likewise),
  *     with the non-equilibrium part of each unknown population taken from
  *     its opposite, then the whole node is regularized and relaxed.
+ *   - Recursive regularized collision (the paper's robust model, Sec. 3.1,
+ *     3.2): third-order Hermite equilibrium; the second-order non-equilibrium
+ *     coefficient is relaxed with 1/tau for its deviatoric part and with 1
+ *     for its trace (bulk relaxation fixed to 1, Sec. 3.1), and the
+ *     third-order non-equilibrium coefficient follows from it recursively
+ *     (after Malaspinas 2015).  Third-order terms use the Hermite polynomials
+ *     the lattice supports, projected with the lattice's own weighted inner
+ *     product.
  *   - Regularized BGK (the regularized family the paper's robust RR model
  *     belongs to, Sec. 3.1-3.2): the non-equilibrium part is replaced by its
  *     projection on the second-order Hermite polynomials before relaxing
@@ -75,9 +83,9 @@ typedef struct {
 /* Open boundaries: T_VIN velocity at x = 0, T_POUT pressure at x = nx-1,
  * T_PIN pressure at x = 0, T_VOUT velocity at x = nx-1. */
 enum { T_SOLID = 0, T_BGK = 1, T_TRT = 2, T_SMAG = 3, T_MLP = 4, T_REG = 5, T_VIN = 6, T_POUT = 7,
-       T_PIN = 8, T_VOUT = 9, T_WALL0 = 16 };
+       T_PIN = 8, T_VOUT = 9, T_RR = 10, T_WALL0 = 16 };
 
-static int is_fluid(int t) { return t >= 1 && t <= 9; }
+static int is_fluid(int t) { return t >= 1 && t <= 10; }
 
 /* ------------------------------------------------------------------ tables */
 /*
@@ -141,6 +149,73 @@ static void equilibrium(const lattice_t *L, double rho, const double u[3], doubl
         double cu = L->c[i][0] * u[0] + L->c[i][1] * u[1] + L->c[i][2] * u[2];
         feq[i] = L->w[i] * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
     }
+}
+
+/* ---------------------------------------------------- third-order Hermite terms */
+/*
+ * Third-order Hermite polynomials H_abc(c) = c_a c_b c_c - cs^2 (c_a d_bc +
+ * c_b d_ac + c_c d_ab), cs^2 = 1/3.  D3Q19 cannot tell H_xxy from H_yzz (and
+ * the other two such pairs) apart under its weighted inner product, so the
+ * basis is built from the sums and differences of those pairs, which are
+ * orthogonal; D3Q27 adds H_xyz.  Each basis polynomial is a signed sum of
+ * H_abc; its coefficient for a symmetric tensor T is the same signed sum of
+ * the T_abc.  The norms are computed from the lattice.
+ */
+#define ORC_NB3 7
+static const int B3_TERMS[ORC_NB3][2][3] = {
+    /* (first term indices), (second term indices); sign from B3_SIGN */
+    {{0, 0, 1}, {1, 2, 2}}, {{0, 0, 1}, {1, 2, 2}},   /* H_xxy +- H_yzz */
+    {{0, 2, 2}, {0, 1, 1}}, {{0, 2, 2}, {0, 1, 1}},   /* H_xzz +- H_xyy */
+    {{1, 1, 2}, {0, 0, 2}}, {{1, 1, 2}, {0, 0, 2}},   /* H_yyz +- H_xxz */
+    {{0, 1, 2}, {0, 1, 2}}};                          /* H_xyz (D3Q27)  */
+static const double B3_SIGN[ORC_NB3] = {1.0, -1.0, 1.0, -1.0, 1.0, -1.0, 0.0};
+
+static double herm3(const int c[3], const int ix[3]) {
+    const double cs2 = 1.0 / 3.0;
+    int a = ix[0], b = ix[1], d = ix[2];
+    return c[a] * c[b] * c[d] - cs2 * (c[a] * (b == d) + c[b] * (a == d) + c[d] * (a == b));
+}
+
+static int basis3_size(int q) { return q == 27 ? 7 : 6; }
+
+static double basis3(int k, const int c[3]) {
+    return herm3(c, B3_TERMS[k][0]) + B3_SIGN[k] * herm3(c, B3_TERMS[k][1]);
+}
+
+static double basis3_coeff(int k, double T[3][3][3]) {
+    const int *a = B3_TERMS[k][0], *b = B3_TERMS[k][1];
+    return T[a[0]][a[1]][a[2]] + B3_SIGN[k] * T[b[0]][b[1]][b[2]];
+}
+
+/* f_i += w_i sum_k P_k(c_i) coeff_k(T) / <P_k, P_k>_w */
+static void add_third_order(const lattice_t *L, double T[3][3][3], double *f) {
+    const int nb = basis3_size(L->q);
+    for (int k = 0; k < nb; ++k) {
+        double nrm = 0.0;
+        for (int i = 0; i < L->q; ++i) {
+            double p = basis3(k, L->c[i]);
+            nrm += L->w[i] * p * p;
+        }
+        const double a = basis3_coeff(k, T) / nrm;
+        for (int i = 0; i < L->q; ++i) f[i] += L->w[i] * basis3(k, L->c[i]) * a;
+    }
+}
+
+/* Third-order Hermite equilibrium: the second-order one plus the projection
+ * of the Maxwellian's third-order coefficient rho u u u. */
+static void equilibrium3(const lattice_t *L, double rho, const double u[3], double *feq) {
+    equilibrium(L, rho, u, feq);
+    double T[3][3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            for (int d = 0; d < 3; ++d) T[a][b][d] = rho * u[a] * u[b] * u[d];
+    add_third_order(L, T, feq);
+}
+
+void orc_equilibrium3(int q, double rho, const double u[3], double *feq) {
+    lattice_t L;
+    make_lattice(q, &L);
+    equilibrium3(&L, rho, u, feq);
 }
 
 void orc_equilibrium(int q, double rho, const double u[3], double *feq) {
@@ -319,7 +394,44 @@ static void collide_node(const orc_config *cfg, const lattice_t *L, int tag,
         tau = tau_eff;
     }
 
-    if (tag == T_REG) {
+    if (tag == T_RR) {
+        /* Recursive regularized collision with Guo forcing.  As for T_REG the
+         * populations read f = feq + f1 - F_i/2 with the momentum flux of f1
+         *   Pi1 = sum c c (f - feq3) + (u F + F u)/2
+         * (feq3 has the same moments up to second order as feq).  After the
+         * collision the second-order non-equilibrium coefficient is
+         *   A2 = (1 - 1/tau) dev(Pi1)            (trace relaxed with 1),
+         * the third-order one follows recursively,
+         *   A3_abc = u_a A2_bc + u_b A2_ac + u_c A2_ab,
+         * and f*_i = feq3_i + w_i [Q_i:A2 / (2 cs^4) + third-order projection
+         * of A3] + F_i / 2. */
+        double fe3[ORC_MAXQ];
+        equilibrium3(L, rho, u, fe3);
+        double Pi1[3][3];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) Pi1[a][b] = 0.5 * (u[a] * F[b] + F[a] * u[b]);
+        for (int i = 0; i < q; ++i) {
+            double d = fin[i] - fe3[i];
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) Pi1[a][b] += L->c[i][a] * L->c[i][b] * d;
+        }
+        const double tr3 = (Pi1[0][0] + Pi1[1][1] + Pi1[2][2]) / 3.0;
+        double A2[3][3], A3[3][3][3];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) A2[a][b] = (1.0 - 1.0 / tau) * (Pi1[a][b] - (a == b ? tr3 : 0.0));
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b)
+                for (int d = 0; d < 3; ++d) A3[a][b][d] = u[a] * A2[b][d] + u[b] * A2[a][d] + u[d] * A2[a][b];
+        const double cs2 = 1.0 / 3.0;
+        for (int i = 0; i < q; ++i) {
+            double qa = 0.0;
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b)
+                    qa += (L->c[i][a] * L->c[i][b] - (a == b ? cs2 : 0.0)) * A2[a][b];
+            fout[i] = fe3[i] + L->w[i] / (2.0 * cs2 * cs2) * qa + 0.5 * (Fev[i] + Fod[i]);
+        }
+        add_third_order(L, A3, fout);
+    } else if (tag == T_REG) {
         /* Regularized BGK.  With Guo forcing the populations read
          *   f = feq + f1 - F_i/2,
          * f1 the first-order (Chapman-Enskog) non-equilibrium part, whose

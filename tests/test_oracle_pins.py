@@ -89,7 +89,7 @@ def _node(q=19, **kw):
 
 
 @pytest.mark.parametrize("q", [19, 27])
-@pytest.mark.parametrize("tag", [oracle.TAG_BGK, oracle.TAG_TRT, oracle.TAG_SMAG, oracle.TAG_REG])
+@pytest.mark.parametrize("tag", [oracle.TAG_BGK, oracle.TAG_TRT, oracle.TAG_SMAG, oracle.TAG_REG, oracle.TAG_RR])
 def test_collision_conserves_mass_and_adds_force(q, tag):
     """sum f* = sum f and sum c f* = sum c f + F (Guo forcing), any model."""
     c, w, _ = oracle.tables(q)
@@ -120,7 +120,7 @@ def test_rest_equilibrium_is_fixed_point():
     for q in (19, 27):
         o = _node(q, tau=0.6)
         f = oracle.equilibrium(q, 1.0, [0, 0, 0])
-        for tag in (oracle.TAG_BGK, oracle.TAG_TRT, oracle.TAG_SMAG, oracle.TAG_REG):
+        for tag in (oracle.TAG_BGK, oracle.TAG_TRT, oracle.TAG_SMAG, oracle.TAG_REG, oracle.TAG_RR):
             fo, _ = o.collide_node(tag, f)
             assert np.abs(fo - f).max() < 4e-16
 
@@ -215,6 +215,79 @@ def test_regularized_couette_and_shear_decay():
         assert np.abs(u[0, 1:-1, 0, 0] - U * (z - 0.5) / (nz - 2)).max() < 1e-10 * U
     e32 = _tgv2d_rate(32, 0.01, 0.8, 100, tag=oracle.TAG_REG)
     e64 = _tgv2d_rate(64, 0.01, 0.8, 400, tag=oracle.TAG_REG)
+    assert e32 < 2e-2 and e32 / e64 >= 3.0
+
+
+@pytest.mark.parametrize("q", [19, 27])
+def test_third_order_equilibrium_moments(q):
+    """The recursive regularized model's equilibrium keeps the second-order one's
+    moments up to order two and has the Maxwellian's third moments
+    sum f c_a^2 c_b = rho (u_a^2 u_b + cs^2 u_b) (a != b) on both lattices, and
+    sum f c_x c_y c_z = rho u_x u_y u_z on D3Q27 (D3Q19 has no such velocity)."""
+    c, w, _ = oracle.tables(q)
+    rho, u, cs2 = 1.05, np.array([0.04, -0.03, 0.05]), 1.0 / 3.0
+    f3, f2 = oracle.equilibrium3(q, rho, u), oracle.equilibrium(q, rho, u)
+    for k in (0, 1, 2):
+        m3 = np.einsum("i,ia,ib->ab", f3, c, c) if k == 2 else (f3 @ c if k == 1 else f3.sum())
+        m2 = np.einsum("i,ia,ib->ab", f2, c, c) if k == 2 else (f2 @ c if k == 1 else f2.sum())
+        assert np.abs(np.asarray(m3) - np.asarray(m2)).max() < 1e-15
+    for a in range(3):
+        for b in range(3):
+            if a != b:
+                ref = rho * (u[a] ** 2 * u[b] + cs2 * u[b])
+                assert abs((f3 * c[:, a] ** 2 * c[:, b]).sum() - ref) < 1e-16
+                assert abs((f2 * c[:, a] ** 2 * c[:, b]).sum() - ref) > 1e-6  # the second-order one misses it
+    if q == 27:
+        assert abs((f3 * c[:, 0] * c[:, 1] * c[:, 2]).sum() - rho * u.prod()) < 1e-17
+
+
+@pytest.mark.parametrize("q", [19, 27])
+def test_recursive_regularized_special_cases(q):
+    """At rest (u = 0, no force) the recursive regularized model equals the
+    regularized one for a traceless non-equilibrium momentum flux, relaxes a
+    purely isotropic one completely (bulk relaxation 1), and at tau = 1 returns
+    the third-order equilibrium plus half the Guo source."""
+    rng = np.random.default_rng(23)
+    tau = 0.66
+    o = _node(q, tau=tau)
+    for _ in range(3):
+        A = 1e-3 * rng.standard_normal((3, 3))
+        A = A + A.T
+        dev = A - np.trace(A) / 3.0 * np.eye(3)
+        feq = oracle.equilibrium(q, 1.01, [0, 0, 0])
+        f = feq + _hermite2(q, dev)
+        a, _ = o.collide_node(oracle.TAG_RR, f)
+        b, _ = o.collide_node(oracle.TAG_REG, f)
+        assert np.abs(a - b).max() < 2e-16
+        f = feq + _hermite2(q, 1e-3 * np.eye(3))
+        a, _ = o.collide_node(oracle.TAG_RR, f)
+        assert np.abs(a - oracle.equilibrium(q, f.sum(), [0, 0, 0])).max() < 2e-16
+    F = np.array([2e-5, -1e-5, 3e-5])
+    o = _node(q, tau=1.0, force=F)
+    c, w, _ = oracle.tables(q)
+    f = oracle.equilibrium(q, 0.98, [0.03, 0.01, -0.02]) + 1e-3 * w * rng.standard_normal(q)
+    a, _ = o.collide_node(oracle.TAG_RR, f)
+    rho = f.sum()
+    u = (f @ c + 0.5 * F) / rho
+    assert np.abs(a - oracle.equilibrium3(q, rho, u) - 0.5 * _guo_source(q, u, F)).max() < 1e-16
+
+
+def test_recursive_regularized_couette_and_shear_decay():
+    """Couette flow with the recursive regularized model is exactly linear with
+    half-way walls, and a z-invariant Taylor-Green vortex decays at 4 nu k^2 to
+    O(k^2) (the bulk relaxation does not touch shear)."""
+    nz, U = 12, 0.02
+    for tau in (0.7, 1.3):
+        tags = inputs.channel_tags(1, 1, nz, top=inputs.TAG_WALL0)
+        tags = np.where(tags == oracle.TAG_BGK, oracle.TAG_RR, tags).astype(np.uint8)
+        o = oracle.Oracle(1, 1, nz, q=19, tau=tau, tags=tags, wall_velocity=[(U, 0, 0)])
+        o.init_equilibrium()
+        o.run(8000)
+        _, u = o.fields()
+        z = np.arange(1, nz - 1)
+        assert np.abs(u[0, 1:-1, 0, 0] - U * (z - 0.5) / (nz - 2)).max() < 1e-10 * U
+    e32 = _tgv2d_rate(32, 0.01, 0.8, 100, tag=oracle.TAG_RR)
+    e64 = _tgv2d_rate(64, 0.01, 0.8, 400, tag=oracle.TAG_RR)
     assert e32 < 2e-2 and e32 / e64 >= 3.0
 
 
@@ -330,7 +403,7 @@ def test_moments_match_exact_sum_of_fields():
     o.run(3)
     m = o.moments()
     r, v = o.fields()
-    fl = (tags >= 1) & (tags <= 9)
+    fl = (tags >= 1) & (tags <= 10)
     uu = (v ** 2).sum(0)
     assert m["n_fluid"] == fl.sum()
     assert abs(m["ke_sum"] - math.fsum((0.5 * uu[fl]).ravel())) <= 2e-16 * m["ke_sum"]
