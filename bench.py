@@ -31,6 +31,7 @@ WORKLOADS = {
     # name: (builder, q, description)
     "cavity256_d3q19_bgk": "D3Q19 BGK lid-driven cavity 256^3, lid u=0.1, Re=1000",
     "cavity256_d3q19_reg": "D3Q19 regularized-BGK lid-driven cavity 256^3, lid u=0.1, Re=1000",
+    "cavity400_d3q19_rr": "D3Q19 recursive-regularized lid-driven cavity 400^3, lid u=0.1, Re=10000",
     "tgv512_d3q27_smag": "D3Q27 BGK+Smagorinsky(Cs=0.1) Taylor-Green 512^3, u0=0.05, Re=1600",
     "porous400_d3q19_trt": "D3Q19 TRT(3/16) body-force porous 400^3, phi=0.20, corr. length 8",
     "tgv32_d3q19_bgk": "D3Q19 BGK Taylor-Green 32^3, u0=0.04, Re=100 (cache-resident)",
@@ -66,6 +67,15 @@ def build_workload(name):
         tags = inputs.cavity_tags(n, fluid_tag=inputs.TAG_REG)
         kw = dict(q=19, tau=3 * nu + 0.5, wall_velocity=[(0.1, 0.0, 0.0)])
         return tags, kw, None, None, {"cells": n ** 3, "lid_u": 0.1, "Re": 1000, "cavity_length": L}
+    if name == "cavity400_d3q19_rr":
+        # the paper's turbulent cavity (Sec. 3.2): Re = 10000 on L = 400 with the
+        # recursive regularized model and bulk relaxation 1
+        n = 400
+        L = n - 2
+        nu = 0.1 * L / 10000.0
+        tags = inputs.cavity_tags(n, fluid_tag=inputs.TAG_RR)
+        kw = dict(q=19, tau=3 * nu + 0.5, wall_velocity=[(0.1, 0.0, 0.0)])
+        return tags, kw, None, None, {"cells": n ** 3, "lid_u": 0.1, "Re": 10000, "cavity_length": L}
     if name == "tgv512_d3q27_smag":
         n, u0, Re = 512, 0.05, 1600.0
         nu = u0 * (n / (2 * np.pi)) / Re
@@ -102,7 +112,7 @@ def build_workload(name):
 def alg_bytes_per_launch(tags, q, prec_bytes):
     """Algorithmic HBM bytes of one collide-stream launch: every fluid node reads
     and writes its Q populations once; every node's tag byte is read once."""
-    fluid = int(np.isin(tags, (1, 2, 3, 4, 5, 6, 7, 8, 9)).sum())
+    fluid = int(np.isin(tags, (1, 2, 3, 4, 5, 6, 7, 8, 9, 10)).sum())
     return fluid * 2 * q * prec_bytes + tags.size, fluid
 
 
@@ -289,7 +299,7 @@ def main():
             ux_mean = r["series"][-1]["velocity_sum"][0] / tags.size
             k_lu = nu * ux_mean / F
             derived[pn] = {"permeability_lu": k_lu, "permeability_mD": k_lu * (5.345e-6) ** 2 / 9.869233e-16,
-                           "porosity": float(np.isin(tags, (1, 2, 3, 4, 5, 6, 7, 8, 9)).mean()),
+                           "porosity": float(np.isin(tags, (1, 2, 3, 4, 5, 6, 7, 8, 9, 10)).mean()),
                            "steps_total": args.warmup + args.steps,
                            "k_series_lu": [nu * m["velocity_sum"][0] / tags.size / F for m in r["series"][::20]]}
         from paper_2506_09242_amd import inputs as _inp
@@ -301,7 +311,7 @@ def main():
         # (mean fluid density of the plane before the rock - of the plane after it)
         nu = (kw["tau"] - 0.5) / 3.0
         buf, n = wl_cfg["buffer"], wl_cfg["rock"]
-        fl = np.isin(tags, (1, 2, 3, 4, 5, 6, 7, 8, 9))
+        fl = np.isin(tags, (1, 2, 3, 4, 5, 6, 7, 8, 9, 10))
         for pn, r in results.items():
             ux = r["u"][0]
             u_mean = float(ux[:, :, buf:buf + n].mean())

@@ -94,6 +94,11 @@ enum {
                               imposes bc_density[0], zero tangential velocity */
     LBM_TAG_VEL_OUT = 9,   /* regularized velocity boundary on the x = nx-1 plane:
                               imposes bc_velocity                             */
+    LBM_TAG_RR = 10,       /* recursive regularized: third-order Hermite
+                              equilibrium, deviatoric second-order and
+                              recursive third-order non-equilibrium, bulk
+                              relaxation 1 (the paper's robust RR model,
+                              Sec. 3.1-3.2)                                   */
     LBM_TAG_WALL0 = 16     /* 16..31: moving wall, velocity wall_velocity[tag-16] */
 };
 /* Open boundaries (tags 6..9; the regularized conditions of Latt et al. 2008

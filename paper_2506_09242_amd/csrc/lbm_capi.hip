@@ -114,7 +114,7 @@ size_t elem_bytes(int prec) { return prec == LBM_F64 ? 8 : (prec == LBM_F32 ? 4 
 // (the blocked layout of pop_base).
 long long pop_elems(long long ncell, int q) { return (ncell + kBlockNodes - 1) / kBlockNodes * kBlockNodes * q; }
 
-bool known_tag(int t) { return (t >= 0 && t <= 9) || (t >= 16 && t <= 31); }
+bool known_tag(int t) { return (t >= 0 && t <= 10) || (t >= 16 && t <= 31); }
 
 // Storage sectors of 64 bytes hold 8 (FP64), 16 (FP32) or 32 (FP16) nodes.
 int sector_log2(int prec) { return prec == LBM_F64 ? 3 : (prec == LBM_F32 ? 4 : 5); }
@@ -127,7 +127,7 @@ long long count_fillers(const uint8_t *tags, long long N, int sector_log2) {
     for (long long a = 0; a < N; a += g) {
         const long long b = a + g < N ? a + g : N;
         long long fl = 0;
-        for (long long k = a; k < b; ++k) fl += (tags[k] >= 1 && tags[k] <= 9);
+        for (long long k = a; k < b; ++k) fl += (tags[k] >= 1 && tags[k] <= 10);
         if (fl) count += (b - a) - fl;
     }
     return count;
@@ -408,7 +408,7 @@ static lbm_status create_impl(const lbm_config *cfg, const uint8_t *tags_host, v
     if (hist[LBM_TAG_PRES_IN] && !(cfg->bc_density[0] > 0.0)) return set_err(LBM_EINVAL, "bc_density[0] must be > 0");
     if (hist[LBM_TAG_PRES_OUT] && !(cfg->bc_density[1] > 0.0)) return set_err(LBM_EINVAL, "bc_density[1] must be > 0");
     long long nf = 0;
-    for (int t = 1; t <= 9; ++t) nf += hist[t];
+    for (int t = 1; t <= 10; ++t) nf += hist[t];
     if (nf == 0) return set_err(LBM_EINVAL, "no fluid node");
     int need = 0;
     if (hist[LBM_TAG_BGK]) need |= MS_BGK;
@@ -417,6 +417,7 @@ static lbm_status create_impl(const lbm_config *cfg, const uint8_t *tags_host, v
     if (hist[LBM_TAG_BGK_MLP]) need |= MS_MLP;
     if (hist[LBM_TAG_REG]) need |= MS_REG;
     if (n_open) need |= MS_OPEN;
+    if (hist[LBM_TAG_RR]) need |= MS_RR;
     int ms = -1;
     for (int k = 0; k < kNumModelSets; ++k)
         if ((kModelSets[k] & need) == need) {
@@ -425,7 +426,7 @@ static lbm_status create_impl(const lbm_config *cfg, const uint8_t *tags_host, v
         }
     if (ms < 0) return set_err(LBM_EUNSUPPORTED, "no compiled model set covers the tags");
     int n_models = 0, only = LBM_TAG_BGK;
-    for (int t = 1; t <= 9; ++t)
+    for (int t = 1; t <= 10; ++t)
         if (hist[t]) {
             n_models++;
             only = t;
@@ -456,7 +457,7 @@ static lbm_status create_impl(const lbm_config *cfg, const uint8_t *tags_host, v
     L->tagged = tagged;
     L->uniform_tag = only;
     choose_tiles(L, default_txl(cfg->nx));
-    static const char *msname[] = {"bgk", "trt", "reg", "bgk+smag", "trt+open", "bgk+smag+mlp", "all"};
+    static const char *msname[] = {"bgk", "trt", "reg", "rr", "bgk+smag", "trt+open", "bgk+smag+mlp", "all"};
     int msi = 0;
     for (int k = 0; k < kNumModelSets; ++k)
         if (kModelSets[k] == ms) msi = k;

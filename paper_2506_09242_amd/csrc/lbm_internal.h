@@ -23,13 +23,15 @@ enum ModelSet : int {
     MS_MLP = 8,
     MS_REG = 16,
     MS_OPEN = 32,  // regularized velocity / pressure boundary nodes on the x planes
+    MS_RR = 64,    // recursive regularized
 };
+constexpr int kAllModels = MS_BGK | MS_TRT | MS_SMAG | MS_MLP | MS_REG | MS_OPEN | MS_RR;
 
 // Compiled model-set variants, smallest first.  The host picks the first one
 // that covers the fluid tags present.
-constexpr int kModelSets[] = {MS_BGK, MS_TRT, MS_REG, MS_BGK | MS_SMAG, MS_TRT | MS_OPEN, MS_BGK | MS_SMAG | MS_MLP,
-                              MS_BGK | MS_TRT | MS_SMAG | MS_MLP | MS_REG | MS_OPEN};
-constexpr int kNumModelSets = 7;
+constexpr int kModelSets[] = {MS_BGK, MS_TRT, MS_REG, MS_RR, MS_BGK | MS_SMAG, MS_TRT | MS_OPEN,
+                              MS_BGK | MS_SMAG | MS_MLP, kAllModels};
+constexpr int kNumModelSets = 8;
 
 // Kernel modes.
 enum StepMode : int {

@@ -222,7 +222,7 @@ __device__ __forceinline__ void collide_node(const C (&h)[Q], int tag, bool live
     }
     // Pi_ab = sum c_a c_b (h - heq): only even parts contribute.
     C pxx = C(0), pyy = C(0), pzz = C(0), pxy = C(0), pxz = C(0), pyz = C(0);
-    if constexpr ((MS & (MS_SMAG | MS_MLP | MS_REG)) != 0) {
+    if constexpr ((MS & (MS_SMAG | MS_MLP | MS_REG | MS_RR)) != 0) {
         sfor<H>([&](auto K) {
             constexpr int k = decltype(K)::value + 1;
             using Vk = V<Q, k>;
@@ -266,13 +266,37 @@ __device__ __forceinline__ void collide_node(const C (&h)[Q], int tag, bool live
     //   f*_i = feq_i + (1 - omega) w_i (9/2) (c_i.Pi1.c_i - tr Pi1 / 3) + F_i / 2,
     // which is the omega = 1 update below (A, B) plus the regularized term added
     // to the even part of each pair.
-    C reg = C(0);  // (1 - omega) * 9/2 on regularized nodes, else 0
+    // Recursive regularized (the paper's RR model, Sec. 3.1-3.2): the same with
+    // the deviatoric part of Pi1 only (bulk relaxation 1), i.e. the even term
+    // (1 - omega) w_i (9/2) (c_i.Pi1.c_i - |c_i|^2 tr Pi1 / 3), plus the odd
+    // third-order Hermite term of T = rho u u u + A3, A3 the recursive
+    // non-equilibrium coefficient A3_abc = u_a A2_bc + u_b A2_ac + u_c A2_ab of
+    // A2 = (1 - omega) dev Pi1.  Third-order polynomials: the sums and
+    // differences of H_xxy and H_yzz, H_xzz and H_xyy, H_yyz and H_xxz
+    // (orthogonal on D3Q19 and D3Q27) and, on D3Q27, H_xyz; each projected with
+    // its lattice norm (D3Q19: 2/27 for sums, 6/27 for differences; D3Q27: 4/27,
+    // and 1/27 for H_xyz).
+    C reg = C(0);      // (1 - omega) * 9/2 on regularized nodes, else 0
+    C trm = C(1);      // 1 (regularized) or 0 (recursive: its trace is relaxed with 1)
+    bool rr = false;   // recursive regularized node
     C rxx = C(0), ryy = C(0), rzz = C(0), rxy = C(0), rxz = C(0), ryz = C(0), rtr = C(0);
-    if constexpr ((MS & MS_REG) != 0) {
-        if (tag == LBM_TAG_REG) {
-            reg = (C(1) - (C)p.omega) * C(4.5);
-            wp = C(1);
-            wm = C(1);
+    C t1p = C(0), t1m = C(0), t2p = C(0), t2m = C(0), t3p = C(0), t3m = C(0), t7 = C(0);
+    if constexpr ((MS & (MS_REG | MS_RR)) != 0) {
+        if constexpr ((MS & MS_REG) != 0) {
+            if (tag == LBM_TAG_REG) {
+                reg = (C(1) - (C)p.omega) * C(4.5);
+                wp = C(1);
+                wm = C(1);
+            }
+        }
+        if constexpr ((MS & MS_RR) != 0) {
+            if (tag == LBM_TAG_RR) {
+                reg = (C(1) - (C)p.omega) * C(4.5);
+                trm = C(0);
+                rr = true;
+                wp = C(1);
+                wm = C(1);
+            }
         }
         rxx = pxx + ux * Fx;
         ryy = pyy + uy * Fy;
@@ -281,12 +305,33 @@ __device__ __forceinline__ void collide_node(const C (&h)[Q], int tag, bool live
         rxz = pxz + C(0.5) * (ux * Fz + uz * Fx);
         ryz = pyz + C(0.5) * (uy * Fz + uz * Fy);
         rtr = (rxx + ryy + rzz) * C(1.0 / 3.0);
+        if constexpr ((MS & MS_RR) != 0) {
+            // A2 = (1 - omega) dev Pi1, A3 recursive, T = rho u u u + A3
+            const C om1 = C(1) - (C)p.omega;
+            const C axx = om1 * (rxx - rtr), ayy = om1 * (ryy - rtr), azz = om1 * (rzz - rtr);
+            const C axy = om1 * rxy, axz = om1 * rxz, ayz = om1 * ryz;
+            const C txxy = rho * ux * ux * uy + C(2) * ux * axy + uy * axx;
+            const C tyzz = rho * uy * uz * uz + uy * azz + C(2) * uz * ayz;
+            const C txzz = rho * ux * uz * uz + ux * azz + C(2) * uz * axz;
+            const C txyy = rho * ux * uy * uy + ux * ayy + C(2) * uy * axy;
+            const C tyyz = rho * uy * uy * uz + C(2) * uy * ayz + uz * ayy;
+            const C txxz = rho * ux * ux * uz + C(2) * ux * axz + uz * axx;
+            constexpr double np_ = Q == 19 ? 27.0 / 2.0 : 27.0 / 4.0;  // 1 / norm of a sum
+            constexpr double nm_ = Q == 19 ? 27.0 / 6.0 : 27.0 / 4.0;  // 1 / norm of a difference
+            t1p = (txxy + tyzz) * C(np_);
+            t1m = (txxy - tyzz) * C(nm_);
+            t2p = (txzz + txyy) * C(np_);
+            t2m = (txzz - txyy) * C(nm_);
+            t3p = (tyyz + txxz) * C(np_);
+            t3m = (tyyz - txxz) * C(nm_);
+            if constexpr (Q == 27) t7 = (rho * ux * uy * uz + ux * ayz + uy * axz + uz * axy) * C(27.0);
+        }
     }
 
     const C gp = C(1) - C(0.5) * wp, gm = C(1) - C(0.5) * wm;
     const C F0 = C(V<Q, 0>::w) * C(-3) * uF;
     hs[0] = h[0] - wp * (h[0] - ev[0]) + gp * F0;
-    if constexpr ((MS & MS_REG) != 0) hs[0] -= reg * C(V<Q, 0>::w) * rtr;
+    if constexpr ((MS & (MS_REG | MS_RR)) != 0) hs[0] -= reg * C(V<Q, 0>::w) * rtr * trm;
     sfor<H>([&](auto K) {
         constexpr int k = decltype(K)::value + 1;
         using Vk = V<Q, k>;
@@ -300,7 +345,8 @@ __device__ __forceinline__ void collide_node(const C (&h)[Q], int tag, bool live
         const C hm = C(0.5) * (h[k] - h[k + H]);
         C A = gp * Fe - wp * (hp - ev[k]);
         const C B = gm * Fo - wm * (hm - od[k]);
-        if constexpr ((MS & MS_REG) != 0) {
+        C Bx = B;
+        if constexpr ((MS & (MS_REG | MS_RR)) != 0) {
             C cpc = C(0);  // c_k . Pi1 . c_k
             if constexpr (Vk::x != 0) cpc += rxx;
             if constexpr (Vk::y != 0) cpc += ryy;
@@ -308,10 +354,29 @@ __device__ __forceinline__ void collide_node(const C (&h)[Q], int tag, bool live
             if constexpr (Vk::x * Vk::y != 0) cpc += C(2 * Vk::x * Vk::y) * rxy;
             if constexpr (Vk::x * Vk::z != 0) cpc += C(2 * Vk::x * Vk::z) * rxz;
             if constexpr (Vk::y * Vk::z != 0) cpc += C(2 * Vk::y * Vk::z) * ryz;
-            A += reg * C(Vk::w) * (cpc - rtr);
+            // regularized: |c|^2 -> 1 (tr Q = 0 projection); recursive: |c|^2 (deviatoric)
+            const C cc = trm + (C(1) - trm) * C(Vk::n2);
+            A += reg * C(Vk::w) * (cpc - rtr * cc);
         }
-        hs[k] = h[k] + A + B;
-        hs[k + H] = h[k + H] + A - B;
+        if constexpr ((MS & MS_RR) != 0) {
+            // odd third-order Hermite term (both equilibrium and non-equilibrium)
+            constexpr int cx = Vk::x, cy = Vk::y, cz = Vk::z;
+            constexpr double p1p = cy * (cx * cx + cz * cz - 2.0 / 3.0), p1m = cy * (cx * cx - cz * cz);
+            constexpr double p2p = cx * (cy * cy + cz * cz - 2.0 / 3.0), p2m = cx * (cz * cz - cy * cy);
+            constexpr double p3p = cz * (cx * cx + cy * cy - 2.0 / 3.0), p3m = cz * (cy * cy - cx * cx);
+            constexpr double p7 = cx * cy * cz;
+            C e3 = C(0);
+            if constexpr (p1p != 0.0) e3 += C(p1p) * t1p;
+            if constexpr (p1m != 0.0) e3 += C(p1m) * t1m;
+            if constexpr (p2p != 0.0) e3 += C(p2p) * t2p;
+            if constexpr (p2m != 0.0) e3 += C(p2m) * t2m;
+            if constexpr (p3p != 0.0) e3 += C(p3p) * t3p;
+            if constexpr (p3m != 0.0) e3 += C(p3m) * t3m;
+            if constexpr (Q == 27 && p7 != 0.0) e3 += C(p7) * t7;
+            if (rr) Bx += C(Vk::w) * e3;
+        }
+        hs[k] = h[k] + A + Bx;
+        hs[k + H] = h[k + H] + A - Bx;
     });
 
     if constexpr ((MS & MS_OPEN) != 0) {
@@ -676,9 +741,8 @@ hipError_t launch_step(const StepParams &p, int ms, bool tagged, int mode, int p
             return launch_step_geo<Q, P, MS_BGK | MS_SMAG | MS_MLP>(p, tagged, mode, parity, s);
         case MS_REG: return launch_step_geo<Q, P, MS_REG>(p, tagged, mode, parity, s);
         case MS_TRT | MS_OPEN: return launch_step_geo<Q, P, MS_TRT | MS_OPEN>(p, tagged, mode, parity, s);
-        case MS_BGK | MS_TRT | MS_SMAG | MS_MLP | MS_REG | MS_OPEN:
-            return launch_step_geo<Q, P, MS_BGK | MS_TRT | MS_SMAG | MS_MLP | MS_REG | MS_OPEN>(p, tagged, mode,
-                                                                                              parity, s);
+        case MS_RR: return launch_step_geo<Q, P, MS_RR>(p, tagged, mode, parity, s);
+        case kAllModels: return launch_step_geo<Q, P, kAllModels>(p, tagged, mode, parity, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -18,6 +18,7 @@ import numpy as np
 
 TAG_SOLID, TAG_BGK, TAG_TRT, TAG_SMAG, TAG_MLP, TAG_REG, TAG_WALL0 = 0, 1, 2, 3, 4, 5, 16
 TAG_VIN, TAG_POUT, TAG_PIN, TAG_VOUT = 6, 7, 8, 9  # open boundaries on the x planes
+TAG_RR = 10
 
 _GOLDEN = np.uint64(0x9E3779B97F4A7C15)
 _M1 = np.uint64(0xBF58476D1CE4E5B9)
@@ -125,7 +126,7 @@ def porous_tags(n: int, porosity=0.20, ell=8.0, seed=42, fluid_tag=TAG_TRT) -> n
 def percolates_x(tags: np.ndarray) -> bool:
     """6-connected fluid path from the x=0 face to the x=nx-1 face."""
     from scipy import ndimage
-    fluid = (tags >= 1) & (tags <= 9)
+    fluid = (tags >= 1) & (tags <= 10)
     lab, _ = ndimage.label(fluid)
     a = set(np.unique(lab[:, :, 0])) - {0}
     b = set(np.unique(lab[:, :, -1])) - {0}

@@ -23,6 +23,7 @@ LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EHIP, LBM_EUNSTABLE, LBM_EUNSUPPORTED, LBM_E
 LBM_F64, LBM_F32, LBM_F16S = 0, 1, 2
 TAG_SOLID, TAG_BGK, TAG_TRT, TAG_SMAG, TAG_MLP, TAG_REG, TAG_WALL0 = 0, 1, 2, 3, 4, 5, 16
 TAG_VIN, TAG_POUT, TAG_PIN, TAG_VOUT = 6, 7, 8, 9  # open boundaries on the x planes
+TAG_RR = 10
 MLP_NPARAMS = 1359
 PREC_NAMES = {"f64": LBM_F64, "f32": LBM_F32, "f16s": LBM_F16S}
 PREC_BYTES = {LBM_F64: 8, LBM_F32: 4, LBM_F16S: 2}

@@ -5,7 +5,7 @@ import numpy as np
 import oracle
 from paper_2506_09242_amd import lbm
 
-FLUID = (1, 2, 3, 4, 5, 6, 7, 8, 9)
+FLUID = (1, 2, 3, 4, 5, 6, 7, 8, 9, 10)
 
 
 def fluid_mask(tags):

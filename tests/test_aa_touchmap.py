@@ -22,7 +22,7 @@ def _setup(q, shape, seed):
     nz, ny, nx = shape
     tags = inputs.random_tags(nx, ny, nz, seed=seed, solid_frac=0.25, wall_frac=0.1)
     c, w, opp = oracle.tables(q)
-    fluid = (tags >= 1) & (tags <= 9)
+    fluid = (tags >= 1) & (tags <= 10)
     return tags, fluid, c, opp
 
 
@@ -109,7 +109,7 @@ def test_aa_free_streaming_matches_push(q, steps):
     # resting walls only: with identity collision the moving-wall term is the
     # one thing that differs between AA (applied at write time) and push
     tags = np.where(tags >= 16, 0, tags).astype(np.uint8)
-    fluid = (tags >= 1) & (tags <= 9)
+    fluid = (tags >= 1) & (tags <= 10)
     rng = np.random.default_rng(steps)
     f0 = rng.uniform(0.5, 1.5, (q,) + shape) * fluid
     nz, ny, nx = shape

@@ -104,7 +104,8 @@ def test_mixed_models_and_walls_fp64(q):
     """Every fluid model and two moving walls in one lattice (the all-model kernel)."""
     nx, ny, nz = 37, 19, 11
     tags = inputs.random_tags(nx, ny, nz, seed=11, solid_frac=0.15, wall_frac=0.1,
-                              fluid_tags=(inputs.TAG_BGK, inputs.TAG_TRT, inputs.TAG_SMAG, inputs.TAG_REG))
+                              fluid_tags=(inputs.TAG_BGK, inputs.TAG_TRT, inputs.TAG_SMAG, inputs.TAG_REG,
+                                          inputs.TAG_RR))
     rho, u = inputs.random_fields(nx, ny, nz, seed=12)
     kw = dict(tau=0.7, smag_cs=0.15, force=(0.0, 1e-5, -1e-5), wall_velocity=[(0.05, 0, 0), (0, -0.04, 0.02)])
     o, L = make_pair(tags, q=q, rho=rho, u=u, **kw)
@@ -113,6 +114,22 @@ def test_mixed_models_and_walls_fp64(q):
     o.run(57)
     err = max_rel_pop_error(L.read_populations(), o.f, tags)
     _print("mixed", q, err)
+    assert err <= TOL
+
+
+@pytest.mark.parametrize("q,steps", [(19, 101), (27, 64)])
+def test_recursive_regularized_cavity_and_force_fp64(q, steps):
+    """Recursive regularized model in a lid-driven cavity with a body force, from
+    a random moving state (the rr-only kernel), odd and even step counts."""
+    n = 22
+    tags = inputs.cavity_tags(n, fluid_tag=inputs.TAG_RR)
+    rho, u = inputs.random_fields(n, n, n, seed=91, du=0.03)
+    o, L = make_pair(tags, q=q, tau=0.53, force=(1e-5, -2e-5, 0.0), wall_velocity=[(0.08, 0, 0)], rho=rho, u=u)
+    assert L.variant == f"D3Q{q}/f64/rr/tagged"
+    L.step(steps)
+    o.run(steps)
+    err = max_rel_pop_error(L.read_populations(), o.f, tags)
+    _print("rr cavity", q, steps, err)
     assert err <= TOL
 
 
