@@ -167,12 +167,21 @@ def cpu_baseline(name, tags, kw, rho, u, steps):
     o = oracle.Oracle(nx, ny, nz, q=kw["q"], tags=tags, **okw)
     o.init_equilibrium(rho, u)
     o.run(1)  # warm-up (first touch of both arrays)
+    cores = oracle.num_threads()
     t0 = time.perf_counter()
     o.run(steps)
     dt = time.perf_counter() - t0
-    return {"value": tags.size * steps / dt / 1e6, "unit": "MLUPS", "cores": oracle.num_threads(),
+    # the same oracle on one thread, one step
+    oracle.set_num_threads(1)
+    t1 = time.perf_counter()
+    o.run(1)
+    dt1 = time.perf_counter() - t1
+    oracle.set_num_threads(cores)
+    return {"value": tags.size * steps / dt / 1e6, "unit": "MLUPS", "cores": cores,
             "kind": "oracle", "sample": f"{steps} FP64 two-population steps of the full {name} lattice "
-                                        f"({tags.size} cells), after 1 warm-up step"}
+                                        f"({tags.size} cells), after 1 warm-up step",
+            "value_single_thread": tags.size / dt1 / 1e6,
+            "sample_single_thread": "1 step of the same lattice on one thread"}
 
 
 def stored_traffic(workload, prec_name):

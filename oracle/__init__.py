@@ -64,6 +64,8 @@ def lib():
         L.orc_mlp_eddy_viscosity.restype = C.c_double
         L.orc_num_threads.argtypes = []
         L.orc_num_threads.restype = C.c_int
+        L.orc_set_num_threads.argtypes = [C.c_int]
+        L.orc_set_num_threads.restype = None
         _lib = L
     return _lib
 
@@ -198,3 +200,7 @@ def enstrophy(u):
 
 def num_threads():
     return lib().orc_num_threads()
+
+
+def set_num_threads(n):
+    lib().orc_set_num_threads(int(n))

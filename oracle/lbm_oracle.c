@@ -639,3 +639,12 @@ int orc_num_threads(void) {
     return 1;
 #endif
 }
+
+/* Set the number of threads later runs use (timing of the CPU baseline). */
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
