@@ -184,7 +184,16 @@ def _stream_handle(stream):
 
 
 class Lattice:
-    """One lattice on the current GPU (owner of an ``lbm_lattice*``)."""
+    """One lattice on the current GPU (owner of an ``lbm_lattice*``).
+
+    tags: uint8 array [nz][ny][nx] (the TAG_* values); prec: LBM_F64 / LBM_F32 /
+    LBM_F16S or "f64" / "f32" / "f16s"; wall_velocity: velocities of the moving
+    wall tags 16, 17, ...; bc_velocity / bc_density: the values imposed by the
+    open-boundary tags (velocity tags 6 and 9; pressure tags 8 on x = 0 and 7 on
+    x = nx-1, densities (x = 0, x = nx-1)); stream: a torch stream or raw
+    handle (default: torch's current stream); torch_buffer: let torch own the
+    population array (lbm_create_on_buffer).
+    """
 
     def __init__(self, tags: np.ndarray, q=19, prec=LBM_F64, tau=0.8, rho0=1.0, trt_lambda=3.0 / 16.0,
                  smag_cs=0.0, force=(0.0, 0.0, 0.0), wall_velocity=None, stream=None, torch_buffer=False,
