@@ -116,12 +116,15 @@ def alg_bytes_per_launch(tags, q, prec_bytes):
     return fluid * 2 * q * prec_bytes + tags.size, fluid
 
 
-def run_dtype(tags, kw, rho, u, prec, steps, warmup, every, repeats=1, chunk=2000, label="", keep_rho=False):
+def run_dtype(tags, kw, rho, u, prec, steps, warmup, every, repeats=1, chunk=2000, label="", keep_rho=False,
+              sample=None):
     """Time `steps` steps (reductions every `every`, fused) after `warmup`, `repeats`
     times back to back on the same lattice.  Long runs go in chunks of about
     `chunk` steps (a multiple of `every`) with one progress line each; the events
     bracket all chunks of one repeat.  The series and the final fields are those
-    of the first repeat (state after warmup + steps)."""
+    of the first repeat (state after warmup + steps).  `sample(L)`, if given, is
+    called on the first repeat after every chunk (and at the start); each chunk
+    is then timed by its own events so that the sampling stays out of the time."""
     import torch
     from paper_2506_09242_amd import lbm
     stream = torch.cuda.current_stream()
@@ -134,14 +137,24 @@ def run_dtype(tags, kw, rho, u, prec, steps, warmup, every, repeats=1, chunk=200
     for rep in range(repeats):
         L.synchronize()
         torch.cuda.synchronize()
+        sampling = sample is not None and rep == 0
+        samples = [(L.time, sample(L))] if sampling else []
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         t0 = time.perf_counter()
         e0.record(stream)
-        series, done = [], 0
+        series, done, chunk_ms = [], 0, 0.0
         while done < steps:
             n = min(chunk, steps - done)
+            if sampling:
+                c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                c0.record(stream)
             part = L.step_reduce(n, every)  # synchronizes at its end
+            if sampling:
+                c1.record(stream)
+                torch.cuda.synchronize()
+                chunk_ms += c0.elapsed_time(c1)
+                samples.append((L.time, sample(L)))
             series.extend(part if not series else part[1:])
             done += n
             if steps > chunk:
@@ -149,10 +162,10 @@ def run_dtype(tags, kw, rho, u, prec, steps, warmup, every, repeats=1, chunk=200
                       flush=True)
         e1.record(stream)
         torch.cuda.synchronize()
-        runs.append(e0.elapsed_time(e1))
+        runs.append(chunk_ms if sampling else e0.elapsed_time(e1))
         if rep == 0:
             rf, uf = L.read_fields()
-            first = {"wall_s": time.perf_counter() - t0, "series": series, "u": uf}
+            first = {"wall_s": time.perf_counter() - t0, "series": series, "u": uf, "samples": samples}
             if keep_rho:
                 first["rho"] = rf
     variant = L.variant
@@ -203,6 +216,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--every", type=int, default=100, help="reduction sampling period (steps)")
     ap.add_argument("--repeats", type=int, default=3, help="timed runs per dtype; the median is reported")
+    ap.add_argument("--enstrophy", action="store_true",
+                    help="sample the enstrophy (Eq. 5 vorticity) after every chunk of the first run")
     ap.add_argument("--workload", default="cavity256_d3q19_bgk", choices=sorted(WORKLOADS))
     ap.add_argument("--dtypes", default="f32,f64,f16s", help="first one is the reported value")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -260,8 +275,9 @@ def main():
     results = {}
     for pn in prec_names:
         prec = lbm.PREC_NAMES[pn]
+        sample = (lambda L: L.enstrophy()) if args.enstrophy else None
         r = run_dtype(tags, kw, rho, u, prec, args.steps, args.warmup, args.every, args.repeats, label=pn,
-                      keep_rho=args.workload == "porous480_open_d3q19_trt")
+                      keep_rho=args.workload == "porous480_open_d3q19_trt", sample=sample)
         nbytes, nfluid = alg_bytes_per_launch(tags, kw["q"], lbm.PREC_BYTES[prec])
         launch_s = r["ms"] * 1e-3 / args.steps
         achieved = nbytes / launch_s / 1e9
@@ -272,7 +288,7 @@ def main():
                        "bytes_per_launch": nbytes, "variant": r["variant"],
                        "runs_ms_per_step": [round(v / args.steps, 5) for v in r["runs_ms"]],
                        "k_final": r["series"][-1]["kinetic_energy"], "series": r["series"], "u": r["u"],
-                       "rho": r.get("rho"),
+                       "rho": r.get("rho"), "samples": r.get("samples"),
                        "wall_s": r["wall_s"]}
         print(f"# {pn}: {results[pn]['MLUPS']:.1f} MLUPS, {achieved:.1f} GB/s algorithmic "
               f"({100 * achieved / HBM_PEAK_GBS:.1f}% of 8 TB/s), {r['variant']}", file=sys.stderr, flush=True)
@@ -351,6 +367,18 @@ def main():
                            "k_final_over_k0": float(k[-1] / k[0]),
                            "t_over_tc": [round(float(v / tc), 3) for v in t[::stride]],
                            "eps_nondim": [float(v) for v in eps[::stride]]}
+            if r.get("samples"):
+                # enstrophy (1/N) sum |curl u|^2 / 2 in units of u0^2 / L_ref^2, L_ref = N / (2 pi);
+                # with the viscous dissipation 2 nu Omega beside eps (the rest is the subgrid model's)
+                nu = (kw["tau"] - 0.5) / 3.0
+                ts = np.array([a for a, _ in r["samples"]], dtype=np.float64)
+                om = np.array([b for _, b in r["samples"]])
+                lref = n / (2 * np.pi)
+                jj = int(np.argmax(om))
+                derived[pn]["enstrophy_t_over_tc"] = [round(float(v / tc), 3) for v in ts]
+                derived[pn]["enstrophy_nondim"] = [float(v * lref ** 2 / u0 ** 2) for v in om]
+                derived[pn]["enstrophy_peak_tc"] = float(ts[jj] / tc)
+                derived[pn]["viscous_eps_nondim"] = [float(2 * nu * v * tc / u0 ** 2) for v in om]
 
     main_p = prec_names[0]
     m = results[main_p]
