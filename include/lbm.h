@@ -182,7 +182,9 @@ void lbm_destroy(lbm_lattice *lat);
 /* Override the launch geometry: 256-thread blocks updating tiles of tx x ty
  * nodes of one z-plane, one node per thread (tx in {32,64,128,256},
  * tx*ty == 256).  Results are bitwise independent of the choice; this exists
- * for tuning and for that test.  EINVAL for other shapes. */
+ * for tuning and for that test.  The shape also decides whether FP16-storage
+ * lattices whose nx is a power of two in [64, 4096] use row-form addressing
+ * (tx >= 64; the variant name then ends in "/rows").  EINVAL for other shapes. */
 lbm_status lbm_set_launch(lbm_lattice *lat, int tx, int ty);
 
 /* ---------------------------------------------------------- initial state */
@@ -323,7 +325,10 @@ int lbm_velocity(int q, int i, int c[3], double *w);
 /* Text of the calling thread's last error ("" if none). */
 const char *lbm_last_error(void);
 
-/* Name of the kernel variant the handle selected (model set, geometry). */
+/* Name of the kernel variant the handle selected: "D3Q<q>/<precision>/<model
+ * set>/<uniform|tagged>", plus "/rows" when the step uses row-form addressing
+ * (a wave's population rows start at wave-uniform addresses).  Owned by the
+ * handle; valid until the next lbm_set_launch or lbm_destroy. */
 const char *lbm_variant_name(const lbm_lattice *lat);
 
 #ifdef __cplusplus

@@ -196,6 +196,16 @@ StepParams step_params(const lbm_lattice *L) {
     p.n_tiles = L->n_tiles;
     p.tiles_per_xcd = (L->n_tiles + 7) / 8;
     p.tx_log2 = L->tx_log2;
+    // Row-form addressing (FP16 storage only, where it pays): whole rows per
+    // 4096-node block (nx a power of two, 64..4096) and a tile at least 64
+    // nodes wide, so that every wave lies in one row of one block.
+    p.row_log2 = -1;
+    if (c.prec == LBM_F16S && L->tx_log2 >= 6 && c.nx >= 64 && c.nx <= (int)kBlockNodes &&
+        (c.nx & (c.nx - 1)) == 0) {
+        int l = 0;
+        while ((c.nx << l) < (int)kBlockNodes) ++l;
+        p.row_log2 = l;
+    }
     p.mask = L->d_mask;
     p.uniform_tag = L->uniform_tag;
     p.has_force = (c.force[0] != 0.0 || c.force[1] != 0.0 || c.force[2] != 0.0) ? 1 : 0;
@@ -212,6 +222,19 @@ StepParams step_params(const lbm_lattice *L) {
     p.bc_rho[1] = c.bc_density[1];
     p.mlp = L->mlp;
     return p;
+}
+
+// Variant name: lattice, precision, model set, geometry, and "/rows" when the
+// step kernels use row-form addressing (depends on the tile shape).
+void name_variant(lbm_lattice *L) {
+    static const char *msname[] = {"bgk", "trt", "reg", "rr", "bgk+smag", "trt+open", "bgk+smag+mlp", "all"};
+    int msi = 0;
+    for (int k = 0; k < kNumModelSets; ++k)
+        if (kModelSets[k] == L->ms) msi = k;
+    const lbm_config &c = L->cfg;
+    snprintf(L->variant, sizeof L->variant, "D3Q%d/%s/%s/%s%s", c.q,
+             c.prec == LBM_F64 ? "f64" : (c.prec == LBM_F32 ? "f32" : "f16s"), msname[msi],
+             L->tagged ? "tagged" : "uniform", step_params(L).row_log2 >= 0 ? "/rows" : "");
 }
 
 AuxParams aux_params(const lbm_lattice *L) {
@@ -457,13 +480,7 @@ static lbm_status create_impl(const lbm_config *cfg, const uint8_t *tags_host, v
     L->tagged = tagged;
     L->uniform_tag = only;
     choose_tiles(L, default_txl(cfg->nx));
-    static const char *msname[] = {"bgk", "trt", "reg", "rr", "bgk+smag", "trt+open", "bgk+smag+mlp", "all"};
-    int msi = 0;
-    for (int k = 0; k < kNumModelSets; ++k)
-        if (kModelSets[k] == ms) msi = k;
-    snprintf(L->variant, sizeof L->variant, "D3Q%d/%s/%s/%s", cfg->q,
-             cfg->prec == LBM_F64 ? "f64" : (cfg->prec == LBM_F32 ? "f32" : "f16s"), msname[msi],
-             tagged ? "tagged" : "uniform");
+    name_variant(L);
 
     auto bail = [&](lbm_status st) {
         lbm_destroy(L);
@@ -578,6 +595,7 @@ extern "C" lbm_status lbm_set_launch(lbm_lattice *lat, int tx, int ty) {
         if (tx == (1 << k)) l = k;
     if (l < 0 || tx * ty != 256) return set_err(LBM_EINVAL, "tile must be tx in {32,64,128,256} with tx*ty = 256");
     choose_tiles(lat, l);
+    name_variant(lat);
     if (lat->tagged) HIPCHK(lat, launch_tile_classify(step_params(lat), lat->d_tile_tag, lat->stream));
     return LBM_OK;
 }

@@ -73,6 +73,8 @@ struct StepParams {
     int n_tiles;              // tiles_x * tiles_y * nz
     int tiles_per_xcd;        // ceil(n_tiles / 8)
     int tx_log2;              // tile width = 1 << tx_log2, height = 256 >> tx_log2
+    int row_log2;             // log2(rows per 4096-node block) when whole rows tile the
+                              // blocks and a tile is at least a wave wide, else -1
     int uniform_tag;          // model tag of every node (untagged variants)
     int has_force;
     int has_mlp;              // closure parameters uploaded

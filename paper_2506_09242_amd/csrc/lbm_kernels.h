@@ -388,7 +388,7 @@ __device__ __forceinline__ void collide_node(const C (&h)[Q], int tag, bool live
 // covering a tile of (1 << tx_log2) x (256 >> tx_log2) nodes of one z-plane.
 // Wall handling selects addresses (never branches around a load or store),
 // so the Q loads of a thread are all in flight together.
-template <int Q, int P, int MS, bool TAGGED, int MODE, int PARITY>
+template <int Q, int P, int MS, bool TAGGED, int MODE, int PARITY, bool ROWS>
 __global__ __launch_bounds__(256) void k_collide_stream(StepParams p) {
     using S = typename Prec<P>::S;
     using C = typename Prec<P>::C;
@@ -427,6 +427,7 @@ __global__ __launch_bounds__(256) void k_collide_stream(StepParams p) {
     int tag = p.uniform_tag;
     uint32_t wall = 0;   // bit i: node x + c_i is not fluid
     bool moving = false; // some neighbour is a moving wall
+    bool plain = !TAGGED;
     if constexpr (TAGGED) {
         // wave-uniform entry read through the constant address space (scalar load)
         typedef const __attribute__((address_space(4))) int const_int;
@@ -434,6 +435,7 @@ __global__ __launch_bounds__(256) void k_collide_stream(StepParams p) {
         const int tile_tag = ((const_int *)p.tile_tag)[L * 4 + wave];
         if (tile_tag != 0) {
             tag = tile_tag;
+            plain = true;
         } else {
             const uint32_t m = active ? p.mask[n] : 0u;
             wall = m & kMaskWalls;
@@ -451,94 +453,186 @@ __global__ __launch_bounds__(256) void k_collide_stream(StepParams p) {
     // Its loaded values are zero and its stored values are never read.
     const bool filler = TAGGED && active && tag == 0 && (wall & 1u);
 
-    // ---- pull the node's populations.  The registers are zeroed first and the
-    // loads sit in a branch with no else: a divergent else that overwrote
-    // registers with loads in flight would force a wait on those loads.
-    C h[Q];
-    sfor<Q>([&](auto I) { h[decltype(I)::value] = C(0); });
-    if (live) {
-        sfor<Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            using Vi = V<Q, i>;
-            long long off;
-            if constexpr (PARITY == 0 || i == 0) {
-                off = pb + slot_off(i);
-            } else {
-                // direction i arrives from x - c_i (slot opp), or from the node's
-                // own slot i when x - c_i is a wall
-                const long long o_nb =
-                    pop_base<Q>(zo[1 - Vi::z] + yo[1 - Vi::y] + xo[1 - Vi::x]) + slot_off(Vi::opp);
-                if constexpr (TAGGED) {
-                    off = ((wall >> Vi::opp) & 1u) ? pb + slot_off(i) : o_nb;
-                } else {
-                    off = o_nb;
-                }
-            }
-            h[i] = (C)f[off];
-        });
-    }
-
     double red[NRED];
     if constexpr (MODE != MODE_STEP) {
 #pragma unroll
         for (int k = 0; k < NRED; ++k) red[k] = 0.0;
-        node_reduce<Q, C>(h, live, p, red);
     }
 
-    if constexpr (MODE != MODE_REDUCE) {
-        C hs[Q];
-        collide_node<Q, C, MS>(h, tag, live, p, hs);
-
-        // moving-wall term where x + c_i is a moving wall (nodes next to one only)
-        if constexpr (TAGGED) {
-            if (moving) {
-                sfor<Q>([&](auto I) {
-                    constexpr int i = decltype(I)::value;
-                    using Vi = V<Q, i>;
-                    if constexpr (i > 0) {
-                        if ((wall >> i) & 1u) {
-                            const int dst = zo[1 + Vi::z] + yo[1 + Vi::y] + xo[1 + Vi::x];
-                            const int t = p.tags[dst];
-                            if (t >= LBM_TAG_WALL0) {
-                                const double *uw = p.wall_u + 3 * (t - LBM_TAG_WALL0);
-                                C cu = C(0);
-                                if constexpr (Vi::x != 0) cu += C(Vi::x) * (C)uw[0];
-                                if constexpr (Vi::y != 0) cu += C(Vi::y) * (C)uw[1];
-                                if constexpr (Vi::z != 0) cu += C(Vi::z) * (C)uw[2];
-                                hs[i] -= C(6.0 * Vi::w) * (C)p.rho0 * cu;
-                            }
-                        }
+    // The node update with either of two address forms.  Row form (ROWS
+    // variants: every wave of an untagged kernel, the plain waves of a tagged
+    // one): whole rows tile the 4096-node blocks and the tile is at least a
+    // wave wide (the host checks both), so the wave's 64 nodes lie in one row
+    // and each population row it reads or writes starts at a wave-uniform
+    // address: a scalar base plus the lane's x offset, no per-lane 64-bit
+    // address arithmetic.  Node form: every address computed per node, with
+    // wall selection.
+    auto update = [&](auto rows_c, auto walls_c) {
+        constexpr bool RF = decltype(rows_c)::value;     // row form
+        constexpr bool WALLS = decltype(walls_c)::value; // wall, filler and moving-wall code
+        // row form: population 0 at x = 0 of row (y + dy, z + dz), index [1 + dz][1 + dy],
+        // and the lane's byte offsets of x - 1, x, x + 1 (periodic)
+        const S *rp[3][3] = {};
+        unsigned xb[3] = {0u, 0u, 0u};
+        if constexpr (RF) {
+            const int ys = __builtin_amdgcn_readfirstlane(y);
+            const int yv[3] = {ys == 0 ? ny - 1 : ys - 1, ys, ys + 1 == ny ? 0 : ys + 1};
+            const int zv[3] = {z == 0 ? nz - 1 : z - 1, z, z + 1 == nz ? 0 : z + 1};
+            const int rl = p.row_log2;
+            sfor<3>([&](auto DZ) {
+                sfor<3>([&](auto DY) {
+                    constexpr int dz = decltype(DZ)::value, dy = decltype(DY)::value;
+                    if (PARITY == 1 || (dz == 1 && dy == 1)) {
+                        const int r = zv[dz] * ny + yv[dy];
+                        rp[dz][dy] = f + (long long)(r >> rl) * (long long)(Q << kBlockLog2) +
+                                     (long long)((r & ((1 << rl) - 1)) * nx);
                     }
                 });
-            }
+            });
+#pragma unroll
+            for (int k = 0; k < 3; ++k) xb[k] = (unsigned)xo[k] * (unsigned)sizeof(S);
         }
+        // Slot base in scalar registers (the empty asm keeps the compiler from
+        // re-associating the slot offset into per-lane 64-bit adds), plus the
+        // lane's 32-bit offset: one global access with a scalar base.
+        typedef __attribute__((address_space(1))) S gS;
+        typedef __attribute__((address_space(1))) char gchar;
+        auto at = [&](const S *row, int slot, unsigned xoff) -> gS * {
+            gS *b = (gS *)(row + slot_off(slot));
+            asm("" : "+s"(b));
+            return (gS *)((gchar *)b + xoff);
+        };
 
-        // ---- push
-        if (live || filler) {
+        // ---- pull the node's populations.  The registers are zeroed first and the
+        // loads sit in a branch with no else: a divergent else that overwrote
+        // registers with loads in flight would force a wait on those loads.
+        C h[Q];
+        sfor<Q>([&](auto I) { h[decltype(I)::value] = C(0); });
+        if (live) {
             sfor<Q>([&](auto I) {
                 constexpr int i = decltype(I)::value;
                 using Vi = V<Q, i>;
-                long long off;
-                bool ok = true;
-                if constexpr (i == 0) {
-                    off = pb;
-                } else if constexpr (PARITY == 0) {
-                    // even step: h*_i goes to slot opp(i) of the node itself
-                    off = pb + slot_off(Vi::opp);
-                } else {
-                    // odd step: h*_i goes to slot i of x + c_i, or back to slot
-                    // opp(i) of the node itself when x + c_i is a wall
-                    off = pop_base<Q>(zo[1 + Vi::z] + yo[1 + Vi::y] + xo[1 + Vi::x]) + slot_off(i);
-                    if constexpr (TAGGED) {
-                        const bool wi = (wall >> i) & 1u;
-                        if (wi) off = live ? pb + slot_off(Vi::opp)
-                                           : pop_base<Q>(zo[1 + Vi::z] + yo[1 + Vi::y] + xo[1]) + slot_off(i);
-                        ok = live || wi;
+                if constexpr (RF) {
+                    if constexpr (PARITY == 0 || i == 0) {
+                        h[i] = (C)*at(rp[1][1], i, xb[1]);
+                    } else {
+                        gS *a = at(rp[1 - Vi::z][1 - Vi::y], Vi::opp, xb[1 - Vi::x]);
+                        if constexpr (WALLS) {
+                            // a wall at x - c_i: the node's own slot i instead
+                            gS *own = at(rp[1][1], i, xb[1]);
+                            a = ((wall >> Vi::opp) & 1u) ? own : a;
+                        }
+                        h[i] = (C)*a;
                     }
+                } else {
+                    long long off;
+                    if constexpr (PARITY == 0 || i == 0) {
+                        off = pb + slot_off(i);
+                    } else {
+                        // direction i arrives from x - c_i (slot opp), or from the node's
+                        // own slot i when x - c_i is a wall
+                        const long long o_nb =
+                            pop_base<Q>(zo[1 - Vi::z] + yo[1 - Vi::y] + xo[1 - Vi::x]) + slot_off(Vi::opp);
+                        if constexpr (TAGGED) {
+                            off = ((wall >> Vi::opp) & 1u) ? pb + slot_off(i) : o_nb;
+                        } else {
+                            off = o_nb;
+                        }
+                    }
+                    h[i] = (C)f[off];
                 }
-                if (ok) f[off] = (S)hs[i];
             });
         }
+
+        if constexpr (MODE != MODE_STEP) node_reduce<Q, C>(h, live, p, red);
+
+        if constexpr (MODE != MODE_REDUCE) {
+            C hs[Q];
+            collide_node<Q, C, MS>(h, tag, live, p, hs);
+
+            // moving-wall term where x + c_i is a moving wall (nodes next to one only)
+            if constexpr (TAGGED && WALLS) {
+                if (moving) {
+                    sfor<Q>([&](auto I) {
+                        constexpr int i = decltype(I)::value;
+                        using Vi = V<Q, i>;
+                        if constexpr (i > 0) {
+                            if ((wall >> i) & 1u) {
+                                const int dst = zo[1 + Vi::z] + yo[1 + Vi::y] + xo[1 + Vi::x];
+                                const int t = p.tags[dst];
+                                if (t >= LBM_TAG_WALL0) {
+                                    const double *uw = p.wall_u + 3 * (t - LBM_TAG_WALL0);
+                                    C cu = C(0);
+                                    if constexpr (Vi::x != 0) cu += C(Vi::x) * (C)uw[0];
+                                    if constexpr (Vi::y != 0) cu += C(Vi::y) * (C)uw[1];
+                                    if constexpr (Vi::z != 0) cu += C(Vi::z) * (C)uw[2];
+                                    hs[i] -= C(6.0 * Vi::w) * (C)p.rho0 * cu;
+                                }
+                            }
+                        }
+                    });
+                }
+            }
+
+            // ---- push
+            if constexpr (RF) {
+                if (live || (WALLS && filler)) {
+                    sfor<Q>([&](auto I) {
+                        constexpr int i = decltype(I)::value;
+                        using Vi = V<Q, i>;
+                        if constexpr (i == 0) {
+                            *at(rp[1][1], 0, xb[1]) = (S)hs[0];
+                        } else if constexpr (PARITY == 0) {
+                            *at(rp[1][1], Vi::opp, xb[1]) = (S)hs[i];
+                        } else if constexpr (!WALLS) {
+                            *at(rp[1 + Vi::z][1 + Vi::y], i, xb[1 + Vi::x]) = (S)hs[i];
+                        } else {
+                            // a wall at x + c_i: back to the node's own slot opp(i), or
+                            // (filler) slot i of x + (0, c_iy, c_iz)
+                            gS *a = at(rp[1 + Vi::z][1 + Vi::y], i, xb[1 + Vi::x]);
+                            const bool wi = (wall >> i) & 1u;
+                            gS *alt = live ? at(rp[1][1], Vi::opp, xb[1]) : at(rp[1 + Vi::z][1 + Vi::y], i, xb[1]);
+                            a = wi ? alt : a;
+                            if (live || wi) *a = (S)hs[i];
+                        }
+                    });
+                }
+            } else if (live || filler) {
+                sfor<Q>([&](auto I) {
+                    constexpr int i = decltype(I)::value;
+                    using Vi = V<Q, i>;
+                    long long off;
+                    bool ok = true;
+                    if constexpr (i == 0) {
+                        off = pb;
+                    } else if constexpr (PARITY == 0) {
+                        // even step: h*_i goes to slot opp(i) of the node itself
+                        off = pb + slot_off(Vi::opp);
+                    } else {
+                        // odd step: h*_i goes to slot i of x + c_i, or back to slot
+                        // opp(i) of the node itself when x + c_i is a wall
+                        off = pop_base<Q>(zo[1 + Vi::z] + yo[1 + Vi::y] + xo[1 + Vi::x]) + slot_off(i);
+                        if constexpr (TAGGED) {
+                            const bool wi = (wall >> i) & 1u;
+                            if (wi) off = live ? pb + slot_off(Vi::opp)
+                                               : pop_base<Q>(zo[1 + Vi::z] + yo[1 + Vi::y] + xo[1]) + slot_off(i);
+                            ok = live || wi;
+                        }
+                    }
+                    if (ok) f[off] = (S)hs[i];
+                });
+            }
+        }
+    };
+    using yes = std::true_type;
+    using no = std::false_type;
+    if constexpr (ROWS && !TAGGED) {
+        update(yes{}, no{});
+    } else if constexpr (ROWS) {
+        if (plain) update(yes{}, no{});
+        else update(yes{}, yes{});
+    } else {
+        update(no{}, std::integral_constant<bool, TAGGED>{});
     }
 
     // ---- per-tile reduction partials (fixed order: shuffle tree, then waves 0..3)
@@ -706,14 +800,28 @@ __global__ __launch_bounds__(256) void k_scatter(AuxParams a) {
 
 // ------------------------------------------------------------- launchers
 
-template <int Q, int P, int MS, bool TG, int MODE>
-static hipError_t launch_step_par(const StepParams &p, int parity, hipStream_t s) {
+template <int Q, int P, int MS, bool TG, int MODE, bool ROWS>
+static hipError_t launch_step_rows(const StepParams &p, int parity, hipStream_t s) {
     const dim3 grid(8 * p.tiles_per_xcd), block(256);
     if (parity == 0)
-        k_collide_stream<Q, P, MS, TG, MODE, 0><<<grid, block, 0, s>>>(p);
+        k_collide_stream<Q, P, MS, TG, MODE, 0, ROWS><<<grid, block, 0, s>>>(p);
     else
-        k_collide_stream<Q, P, MS, TG, MODE, 1><<<grid, block, 0, s>>>(p);
+        k_collide_stream<Q, P, MS, TG, MODE, 1, ROWS><<<grid, block, 0, s>>>(p);
     return hipGetLastError();
+}
+
+// Row-form variants (see k_collide_stream) in FP16 storage, where the lattice
+// allows them.  There the node form's per-lane address arithmetic limits the
+// step (the odd step most); in FP32/FP64 the step is bound by memory alone and
+// the row form measured 0.5-3% slower (all its loads leave at once), so those
+// precisions keep the node form.
+template <int Q, int P, int MS, bool TG, int MODE>
+static hipError_t launch_step_par(const StepParams &p, int parity, hipStream_t s) {
+    constexpr bool kRows = P == 2;
+    if constexpr (kRows) {
+        if (p.row_log2 >= 0) return launch_step_rows<Q, P, MS, TG, MODE, true>(p, parity, s);
+    }
+    return launch_step_rows<Q, P, MS, TG, MODE, false>(p, parity, s);
 }
 
 template <int Q, int P, int MS, bool TG>

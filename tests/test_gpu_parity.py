@@ -249,6 +249,56 @@ def test_launch_shape_is_bitwise_irrelevant(prec):
         assert np.array_equal(f, outs[0])
 
 
+
+# Row-form addressing (FP16 storage, nx a power of two in [64, 4096], tiles at
+# least 64 wide) must give exactly the node-form result (tiles 32 wide): the
+# arithmetic is the same, only the addresses are formed differently.
+@pytest.mark.parametrize("q,nx,ny,nz,kind", [
+    (19, 64, 21, 9, "walls"), (27, 128, 10, 7, "walls"), (19, 4096, 3, 2, "walls"),
+    (19, 64, 5, 11, "periodic"), (27, 128, 9, 4, "periodic"), (19, 256, 6, 5, "cavity")])
+def test_row_form_matches_node_form_f16(q, nx, ny, nz, kind):
+    if kind == "walls":
+        tags = inputs.random_tags(nx, ny, nz, seed=nx + ny, solid_frac=0.1, wall_frac=0.03)
+        kw = dict(tau=0.8, wall_velocity=[(0.05, 0, 0), (0, 0.02, 0)])
+    elif kind == "periodic":
+        # D3Q27: the Smagorinsky model with a body force; D3Q19: plain BGK
+        tags = inputs.all_fluid(nx, ny, nz, tag=inputs.TAG_SMAG if q == 27 else inputs.TAG_BGK)
+        kw = dict(tau=0.52, smag_cs=0.1, force=(1e-5, 0, 0)) if q == 27 else dict(tau=0.7)
+    else:
+        tags = _box_cavity(nx, ny, nz)
+        kw = dict(tau=0.6, wall_velocity=[(0.1, 0, 0)])
+    rho, u = inputs.random_fields(nx, ny, nz, seed=7)
+    outs, sers, names = [], [], []
+    for tx in (32, 64, 256):
+        L = lbm.Lattice(tags, q=q, prec=lbm.LBM_F16S, **kw)
+        L.set_launch(tx, 256 // tx)
+        names.append(L.variant)
+        L.init_equilibrium(rho, u)
+        sers.append(L.step_reduce(9, 3))
+        L.step(4)
+        outs.append(L.read_populations())
+        L.close()
+    _print(q, nx, ny, nz, kind, names)
+    assert not names[0].endswith("/rows") and all(n.endswith("/rows") for n in names[1:])
+    for f, ser in zip(outs[1:], sers[1:]):
+        assert np.array_equal(f, outs[0])
+        # reductions: the per-tile partials follow the tile shape, so the FP64
+        # sums differ in summation order only
+        for a, b in zip(ser, sers[0]):
+            assert a.keys() == b.keys()
+            for k in a:
+                assert np.allclose(a[k], b[k], rtol=1e-12, atol=1e-10), k
+
+
+def _box_cavity(nx, ny, nz):
+    """Walls on all six faces, a moving lid (tag 16) on the top plane."""
+    t = np.ones((nz, ny, nx), np.uint8)
+    t[:, :, 0] = t[:, :, -1] = 0
+    t[:, 0, :] = t[:, -1, :] = 0
+    t[0] = 0
+    t[-1] = 16
+    return t
+
 def test_reductions_repeatable():
     n = 40
     rho, u = inputs.tgv3d_fields(n, 0.05)
