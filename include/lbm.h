@@ -182,9 +182,10 @@ void lbm_destroy(lbm_lattice *lat);
 /* Override the launch geometry: 256-thread blocks updating tiles of tx x ty
  * nodes of one z-plane, one node per thread (tx in {32,64,128,256},
  * tx*ty == 256).  Results are bitwise independent of the choice; this exists
- * for tuning and for that test.  The shape also decides whether FP16-storage
- * lattices whose nx is a power of two in [64, 4096] use row-form addressing
- * (tx >= 64; the variant name then ends in "/rows").  EINVAL for other shapes. */
+ * for tuning and for that test.  The shape also decides whether a lattice
+ * whose nx is a power of two in [64, 4096] uses row-form addressing (tx >= 64;
+ * FP16 storage, or a tagged lattice in any precision; the variant name then
+ * ends in "/rows").  EINVAL for other shapes. */
 lbm_status lbm_set_launch(lbm_lattice *lat, int tx, int ty);
 
 /* ---------------------------------------------------------- initial state */

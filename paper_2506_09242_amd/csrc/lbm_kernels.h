@@ -460,13 +460,13 @@ __global__ __launch_bounds__(256) void k_collide_stream(StepParams p) {
     }
 
     // The node update with either of two address forms.  Row form (ROWS
-    // variants: every wave of an untagged kernel, the plain waves of a tagged
-    // one): whole rows tile the 4096-node blocks and the tile is at least a
-    // wave wide (the host checks both), so the wave's 64 nodes lie in one row
-    // and each population row it reads or writes starts at a wave-uniform
-    // address: a scalar base plus the lane's x offset, no per-lane 64-bit
-    // address arithmetic.  Node form: every address computed per node, with
-    // wall selection.
+    // variants; which waves use it is chosen below): whole rows tile the
+    // 4096-node blocks and the tile is at least a wave wide (the host checks
+    // both), so the wave's 64 nodes lie in one row and each population row it
+    // reads or writes starts at a wave-uniform address: a scalar base plus the
+    // lane's x offset, no per-lane 64-bit address arithmetic (wall waves
+    // select per lane between two such addresses).  Node form: every address
+    // computed per node, with wall selection.
     auto update = [&](auto rows_c, auto walls_c) {
         constexpr bool RF = decltype(rows_c)::value;     // row form
         constexpr bool WALLS = decltype(walls_c)::value; // wall, filler and moving-wall code
@@ -628,8 +628,11 @@ __global__ __launch_bounds__(256) void k_collide_stream(StepParams p) {
     using no = std::false_type;
     if constexpr (ROWS && !TAGGED) {
         update(yes{}, no{});
-    } else if constexpr (ROWS) {
+    } else if constexpr (ROWS && P == 2) {
         if (plain) update(yes{}, no{});
+        else update(yes{}, yes{});
+    } else if constexpr (ROWS) {
+        if (plain) update(no{}, yes{});
         else update(yes{}, yes{});
     } else {
         update(no{}, std::integral_constant<bool, TAGGED>{});
@@ -810,14 +813,15 @@ static hipError_t launch_step_rows(const StepParams &p, int parity, hipStream_t 
     return hipGetLastError();
 }
 
-// Row-form variants (see k_collide_stream) in FP16 storage, where the lattice
-// allows them.  There the node form's per-lane address arithmetic limits the
-// step (the odd step most); in FP32/FP64 the step is bound by memory alone and
-// the row form measured 0.5-3% slower (all its loads leave at once), so those
-// precisions keep the node form.
+// Row-form variants (see k_collide_stream) where the lattice allows them: in
+// FP16 storage for every wave (there the node form's per-lane address
+// arithmetic limits the step, the odd step most), in FP32/FP64 for the wall
+// waves of tagged lattices only (their selects get cheaper; for plain waves
+// and untagged lattices, bound by memory alone, the row form measured 0.5-3%
+// slower than the node form).
 template <int Q, int P, int MS, bool TG, int MODE>
 static hipError_t launch_step_par(const StepParams &p, int parity, hipStream_t s) {
-    constexpr bool kRows = P == 2;
+    constexpr bool kRows = P == 2 || TG;
     if constexpr (kRows) {
         if (p.row_log2 >= 0) return launch_step_rows<Q, P, MS, TG, MODE, true>(p, parity, s);
     }

@@ -250,13 +250,19 @@ def test_launch_shape_is_bitwise_irrelevant(prec):
 
 
 
-# Row-form addressing (FP16 storage, nx a power of two in [64, 4096], tiles at
-# least 64 wide) must give exactly the node-form result (tiles 32 wide): the
-# arithmetic is the same, only the addresses are formed differently.
-@pytest.mark.parametrize("q,nx,ny,nz,kind", [
-    (19, 64, 21, 9, "walls"), (27, 128, 10, 7, "walls"), (19, 4096, 3, 2, "walls"),
-    (19, 64, 5, 11, "periodic"), (27, 128, 9, 4, "periodic"), (19, 256, 6, 5, "cavity")])
-def test_row_form_matches_node_form_f16(q, nx, ny, nz, kind):
+# Row-form addressing (nx a power of two in [64, 4096], tiles at least 64 wide;
+# every wave in FP16 storage, the wall waves of tagged lattices in FP32/FP64)
+# must give exactly the node-form result (tiles 32 wide): the arithmetic is
+# the same, only the addresses are formed differently.
+F16S, F32, F64 = lbm.LBM_F16S, lbm.LBM_F32, lbm.LBM_F64
+
+
+@pytest.mark.parametrize("prec,q,nx,ny,nz,kind", [
+    (F16S, 19, 64, 21, 9, "walls"), (F16S, 27, 128, 10, 7, "walls"), (F16S, 19, 4096, 3, 2, "walls"),
+    (F16S, 19, 64, 5, 11, "periodic"), (F16S, 27, 128, 9, 4, "periodic"), (F16S, 19, 256, 6, 5, "cavity"),
+    (F32, 19, 64, 21, 9, "walls"), (F32, 27, 128, 10, 7, "walls"), (F32, 19, 256, 6, 5, "cavity"),
+    (F64, 19, 64, 21, 9, "walls"), (F64, 27, 256, 6, 5, "cavity")])
+def test_row_form_matches_node_form(prec, q, nx, ny, nz, kind):
     if kind == "walls":
         tags = inputs.random_tags(nx, ny, nz, seed=nx + ny, solid_frac=0.1, wall_frac=0.03)
         kw = dict(tau=0.8, wall_velocity=[(0.05, 0, 0), (0, 0.02, 0)])
@@ -270,7 +276,7 @@ def test_row_form_matches_node_form_f16(q, nx, ny, nz, kind):
     rho, u = inputs.random_fields(nx, ny, nz, seed=7)
     outs, sers, names = [], [], []
     for tx in (32, 64, 256):
-        L = lbm.Lattice(tags, q=q, prec=lbm.LBM_F16S, **kw)
+        L = lbm.Lattice(tags, q=q, prec=prec, **kw)
         L.set_launch(tx, 256 // tx)
         names.append(L.variant)
         L.init_equilibrium(rho, u)
@@ -278,7 +284,7 @@ def test_row_form_matches_node_form_f16(q, nx, ny, nz, kind):
         L.step(4)
         outs.append(L.read_populations())
         L.close()
-    _print(q, nx, ny, nz, kind, names)
+    _print(prec, q, nx, ny, nz, kind, names)
     assert not names[0].endswith("/rows") and all(n.endswith("/rows") for n in names[1:])
     for f, ser in zip(outs[1:], sers[1:]):
         assert np.array_equal(f, outs[0])
