@@ -447,13 +447,15 @@ def _bench_workload(name):
     return bench.build_workload(name)
 
 
-@pytest.mark.parametrize("prec,bound", [(lbm.LBM_F64, TOL), (lbm.LBM_F32, 1e-5)])
+# FP16 storage: each step rounds h = f - w rho0 once (unit roundoff 2^-11), and
+# |h| <= f next to the moving lid, so 11 steps stay within 11 * 2^-11 of f.
+@pytest.mark.parametrize("prec,bound", [(lbm.LBM_F64, TOL), (lbm.LBM_F32, 1e-5), (lbm.LBM_F16S, 11 * 2.0**-11)])
 def test_full_size_cavity_sampled_cells(prec, bound):
     """The benchmark's workload at its full size and launch configuration (the
     256^3 lid-driven cavity, default tiling) from a random near-rest state, 11
     steps: sampled cells (all lid-adjacent nodes of four rows, the x-wall
     columns, and random nodes) match the oracle's populations (FP64 to 1e-12
-    relative; FP32 storage within 1e-5)."""
+    relative; FP32 storage within 1e-5; FP16 storage within its rounding bound)."""
     tags, kw, _, _, _ = _bench_workload("cavity256_d3q19_bgk")
     nz, ny, nx = tags.shape
     rho, u = inputs.random_fields(nx, ny, nz, seed=77, du=0.01, drho=0.005)
