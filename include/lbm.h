@@ -184,8 +184,8 @@ void lbm_destroy(lbm_lattice *lat);
  * tx*ty == 256).  Results are bitwise independent of the choice; this exists
  * for tuning and for that test.  The shape also decides whether a lattice
  * whose nx is a power of two in [64, 4096] uses row-form addressing (tx >= 64;
- * FP16 storage, or a tagged lattice in any precision; the variant name then
- * ends in "/rows").  EINVAL for other shapes. */
+ * FP16 storage, or a tagged lattice with at least half of its nodes fluid; the
+ * variant name then ends in "/rows").  EINVAL for other shapes. */
 lbm_status lbm_set_launch(lbm_lattice *lat, int tx, int ty);
 
 /* ---------------------------------------------------------- initial state */

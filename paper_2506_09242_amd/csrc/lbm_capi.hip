@@ -196,12 +196,15 @@ StepParams step_params(const lbm_lattice *L) {
     p.n_tiles = L->n_tiles;
     p.tiles_per_xcd = (L->n_tiles + 7) / 8;
     p.tx_log2 = L->tx_log2;
-    // Row-form addressing (FP16 storage, and the wall waves of tagged lattices,
-    // where it pays): whole rows per 4096-node block (nx a power of two,
-    // 64..4096) and a tile at least 64 nodes wide, so that every wave lies in
-    // one row of one block.
+    // Row-form addressing where it pays: FP16 storage, and in FP32/FP64 the
+    // wall waves of tagged lattices that are mostly fluid (measured: a
+    // walled cavity gains, a porous medium with 80% solid loses).  Needs
+    // whole rows per 4096-node block (nx a power of two, 64..4096) and a tile
+    // at least 64 nodes wide, so that every wave lies in one row of one block.
+    const long long n_nodes = (long long)c.nx * c.ny * c.nz;
+    const bool rows_pay = c.prec == LBM_F16S || (L->tagged && 2 * L->n_fluid >= n_nodes);
     p.row_log2 = -1;
-    if ((c.prec == LBM_F16S || L->tagged) && L->tx_log2 >= 6 && c.nx >= 64 && c.nx <= (int)kBlockNodes &&
+    if (rows_pay && L->tx_log2 >= 6 && c.nx >= 64 && c.nx <= (int)kBlockNodes &&
         (c.nx & (c.nx - 1)) == 0) {
         int l = 0;
         while ((c.nx << l) < (int)kBlockNodes) ++l;

@@ -386,8 +386,8 @@ __device__ __forceinline__ void collide_node(const C (&h)[Q], int tag, bool live
 
 // The fused collide-and-stream step: one thread per node, 256-thread blocks
 // covering a tile of (1 << tx_log2) x (256 >> tx_log2) nodes of one z-plane.
-// Wall handling selects addresses (never branches around a load or store),
-// so the Q loads of a thread are all in flight together.
+// Wall handling selects addresses rather than branching around loads, so the
+// Q loads of a thread are all in flight together.
 template <int Q, int P, int MS, bool TAGGED, int MODE, int PARITY, bool ROWS>
 __global__ __launch_bounds__(256) void k_collide_stream(StepParams p) {
     using S = typename Prec<P>::S;
@@ -492,9 +492,10 @@ __global__ __launch_bounds__(256) void k_collide_stream(StepParams p) {
 #pragma unroll
             for (int k = 0; k < 3; ++k) xb[k] = (unsigned)xo[k] * (unsigned)sizeof(S);
         }
-        // Slot base in scalar registers (the empty asm keeps the compiler from
-        // re-associating the slot offset into per-lane 64-bit adds), plus the
-        // lane's 32-bit offset: one global access with a scalar base.
+        // Slot base in scalar registers (wave-uniform: the row bases derive from
+        // the wave's row; the empty asm keeps the compiler from re-associating
+        // the slot offset into per-lane 64-bit adds), plus the lane's 32-bit
+        // offset: one global access with a scalar base.
         typedef __attribute__((address_space(1))) S gS;
         typedef __attribute__((address_space(1))) char gchar;
         auto at = [&](const S *row, int slot, unsigned xoff) -> gS * {
