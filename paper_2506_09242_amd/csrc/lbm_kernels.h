@@ -174,8 +174,138 @@ __device__ __forceinline__ void open_boundary(const C (&h)[Q], int tag, const St
 
 // Collision of one node in shifted form (pair split, Guo forcing).  Every lane
 // of the wave must call it (the learned closure is evaluated wave-wide).
+// Regularized and recursive-regularized update for lattices whose fluid nodes
+// all use one of those two models.  Both relax to a state built from the
+// moments alone (rho, u and the non-equilibrium momentum flux), so the update
+// needs the populations only for the moment sums: the flux comes from the
+// second moment of h minus that of the equilibrium,
+//   Pi_ab = sum c_a c_b h - drho / 3 delta_ab - rho u_a u_b
+// (h = f - w rho0; the second-order equilibrium's second moment is
+// rho / 3 delta + rho u u on D3Q19 and D3Q27), and the post-collision pair
+// (k, k + H) is feq_k + F_k / 2 + the regularized (and third-order) terms,
+// with the odd parts entering with opposite signs.  The same algebra as the
+// general path with omega = 1 in its relaxation, where h cancels; only the
+// rounding differs.  Keeping no population live across the update frees the
+// registers the general path needs.
 template <int Q, typename C, int MS>
+__device__ __forceinline__ void collide_regularized(const C (&h)[Q], int tag, const StepParams &p, C (&hs)[Q]) {
+    constexpr int H = (Q - 1) / 2;
+    constexpr bool RR = MS == MS_RR;
+    C drho = C(0), jx = C(0), jy = C(0), jz = C(0);
+    C sxx = C(0), syy = C(0), szz = C(0), sxy = C(0), sxz = C(0), syz = C(0);
+    sfor<Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        using Vi = V<Q, i>;
+        drho += h[i];
+        if constexpr (Vi::x == 1) jx += h[i];
+        if constexpr (Vi::x == -1) jx -= h[i];
+        if constexpr (Vi::y == 1) jy += h[i];
+        if constexpr (Vi::y == -1) jy -= h[i];
+        if constexpr (Vi::z == 1) jz += h[i];
+        if constexpr (Vi::z == -1) jz -= h[i];
+        if constexpr (Vi::x != 0) sxx += h[i];
+        if constexpr (Vi::y != 0) syy += h[i];
+        if constexpr (Vi::z != 0) szz += h[i];
+        if constexpr (Vi::x * Vi::y == 1) sxy += h[i];
+        if constexpr (Vi::x * Vi::y == -1) sxy -= h[i];
+        if constexpr (Vi::x * Vi::z == 1) sxz += h[i];
+        if constexpr (Vi::x * Vi::z == -1) sxz -= h[i];
+        if constexpr (Vi::y * Vi::z == 1) syz += h[i];
+        if constexpr (Vi::y * Vi::z == -1) syz -= h[i];
+    });
+    const C Fx = (C)p.force[0], Fy = (C)p.force[1], Fz = (C)p.force[2];
+    const C rho = (C)p.rho0 + drho;
+    const C inv_rho = C(1) / rho;
+    const C ux = (jx + C(0.5) * Fx) * inv_rho;
+    const C uy = (jy + C(0.5) * Fy) * inv_rho;
+    const C uz = (jz + C(0.5) * Fz) * inv_rho;
+    const C uu = ux * ux + uy * uy + uz * uz;
+    const C uF = ux * Fx + uy * Fy + uz * Fz;
+    const C d3 = drho * C(1.0 / 3.0);
+    // Pi1 = Pi + (uF + Fu) / 2
+    const C rxx = sxx - d3 - rho * ux * ux + ux * Fx;
+    const C ryy = syy - d3 - rho * uy * uy + uy * Fy;
+    const C rzz = szz - d3 - rho * uz * uz + uz * Fz;
+    const C rxy = sxy - rho * ux * uy + C(0.5) * (ux * Fy + uy * Fx);
+    const C rxz = sxz - rho * ux * uz + C(0.5) * (ux * Fz + uz * Fx);
+    const C ryz = syz - rho * uy * uz + C(0.5) * (uy * Fz + uz * Fy);
+    const C rtr = (rxx + ryy + rzz) * C(1.0 / 3.0);
+    const bool on = tag == (RR ? LBM_TAG_RR : LBM_TAG_REG);
+    const C om1 = C(1) - (C)p.omega;
+    const C reg = on ? om1 * C(4.5) : C(0);
+    C t1p = C(0), t1m = C(0), t2p = C(0), t2m = C(0), t3p = C(0), t3m = C(0), t7 = C(0);
+    if constexpr (RR) {
+        // A2 = (1 - omega) dev Pi1, A3 recursive, T = rho u u u + A3
+        const C axx = om1 * (rxx - rtr), ayy = om1 * (ryy - rtr), azz = om1 * (rzz - rtr);
+        const C axy = om1 * rxy, axz = om1 * rxz, ayz = om1 * ryz;
+        const C txxy = rho * ux * ux * uy + C(2) * ux * axy + uy * axx;
+        const C tyzz = rho * uy * uz * uz + uy * azz + C(2) * uz * ayz;
+        const C txzz = rho * ux * uz * uz + ux * azz + C(2) * uz * axz;
+        const C txyy = rho * ux * uy * uy + ux * ayy + C(2) * uy * axy;
+        const C tyyz = rho * uy * uy * uz + C(2) * uy * ayz + uz * ayy;
+        const C txxz = rho * ux * ux * uz + C(2) * ux * axz + uz * axx;
+        constexpr double np_ = Q == 19 ? 27.0 / 2.0 : 27.0 / 4.0;  // 1 / norm of a sum
+        constexpr double nm_ = Q == 19 ? 27.0 / 6.0 : 27.0 / 4.0;  // 1 / norm of a difference
+        const C g = on ? C(1) : C(0);
+        t1p = g * (txxy + tyzz) * C(np_);
+        t1m = g * (txxy - tyzz) * C(nm_);
+        t2p = g * (txzz + txyy) * C(np_);
+        t2m = g * (txzz - txyy) * C(nm_);
+        t3p = g * (tyyz + txxz) * C(np_);
+        t3m = g * (tyyz - txxz) * C(nm_);
+        if constexpr (Q == 27) t7 = g * (rho * ux * uy * uz + ux * ayz + uy * axz + uz * axy) * C(27.0);
+    }
+
+    // rest population: regularized keeps the trace term, recursive relaxes it with 1
+    hs[0] = C(V<Q, 0>::w) * (drho - C(1.5) * rho * uu - C(1.5) * uF);
+    if constexpr (!RR) hs[0] -= reg * C(V<Q, 0>::w) * rtr;
+    sfor<H>([&](auto K) {
+        constexpr int k = decltype(K)::value + 1;
+        using Vk = V<Q, k>;
+        C cu = C(0), cF = C(0), cpc = C(0);
+        if constexpr (Vk::x != 0) cu += C(Vk::x) * ux, cF += C(Vk::x) * Fx, cpc += rxx;
+        if constexpr (Vk::y != 0) cu += C(Vk::y) * uy, cF += C(Vk::y) * Fy, cpc += ryy;
+        if constexpr (Vk::z != 0) cu += C(Vk::z) * uz, cF += C(Vk::z) * Fz, cpc += rzz;
+        if constexpr (Vk::x * Vk::y != 0) cpc += C(2 * Vk::x * Vk::y) * rxy;
+        if constexpr (Vk::x * Vk::z != 0) cpc += C(2 * Vk::x * Vk::z) * rxz;
+        if constexpr (Vk::y * Vk::z != 0) cpc += C(2 * Vk::y * Vk::z) * ryz;
+        const C ev = C(Vk::w) * (drho + rho * (C(4.5) * cu * cu - C(1.5) * uu));
+        const C od = C(Vk::w) * C(3) * rho * cu;
+        const C Fe = C(Vk::w) * (C(9) * cu * cF - C(3) * uF);
+        const C Fo = C(Vk::w) * C(3) * cF;
+        // regularized: |c|^2 -> 1 (tr Q = 0 projection); recursive: |c|^2 (deviatoric)
+        const C R = reg * C(Vk::w) * (cpc - rtr * C(RR ? Vk::n2 : 1));
+        C E = C(0);
+        if constexpr (RR) {
+            constexpr int cx = Vk::x, cy = Vk::y, cz = Vk::z;
+            constexpr double p1p = cy * (cx * cx + cz * cz - 2.0 / 3.0), p1m = cy * (cx * cx - cz * cz);
+            constexpr double p2p = cx * (cy * cy + cz * cz - 2.0 / 3.0), p2m = cx * (cz * cz - cy * cy);
+            constexpr double p3p = cz * (cx * cx + cy * cy - 2.0 / 3.0), p3m = cz * (cy * cy - cx * cx);
+            constexpr double p7 = cx * cy * cz;
+            if constexpr (p1p != 0.0) E += C(p1p) * t1p;
+            if constexpr (p1m != 0.0) E += C(p1m) * t1m;
+            if constexpr (p2p != 0.0) E += C(p2p) * t2p;
+            if constexpr (p2m != 0.0) E += C(p2m) * t2m;
+            if constexpr (p3p != 0.0) E += C(p3p) * t3p;
+            if constexpr (p3m != 0.0) E += C(p3m) * t3m;
+            if constexpr (Q == 27 && p7 != 0.0) E += C(p7) * t7;
+            E *= C(Vk::w);
+        }
+        const C A = ev + C(0.5) * Fe + R;
+        const C B = od + C(0.5) * Fo + E;
+        hs[k] = A + B;
+        hs[k + H] = A - B;
+    });
+}
+
+// MOM: regularized / recursive-regularized lattices take the moment-only
+// update (collide_regularized); the caller decides where that pays.
+template <int Q, typename C, int MS, bool MOM = false>
 __device__ __forceinline__ void collide_node(const C (&h)[Q], int tag, bool live, const StepParams &p, C (&hs)[Q]) {
+    if constexpr (MOM && (MS == MS_REG || MS == MS_RR)) {
+        collide_regularized<Q, C, MS>(h, tag, p, hs);
+        return;
+    }
     constexpr int H = (Q - 1) / 2;
     C drho = C(0), jx = C(0), jy = C(0), jz = C(0);
     sfor<Q>([&](auto I) {
@@ -549,7 +679,10 @@ __global__ __launch_bounds__(256) void k_collide_stream(StepParams p) {
 
         if constexpr (MODE != MODE_REDUCE) {
             C hs[Q];
-            collide_node<Q, C, MS>(h, tag, live, p, hs);
+            // moment-only regularized update in FP16 storage and FP64 (fewer
+            // registers: FP16 +10-14%, FP64 RR +4%); FP32 measured 0.5-2%
+            // slower with it and keeps the general update
+            collide_node<Q, C, MS, P != 1>(h, tag, live, p, hs);
 
             // moving-wall term where x + c_i is a moving wall (nodes next to one only)
             if constexpr (TAGGED && WALLS) {
