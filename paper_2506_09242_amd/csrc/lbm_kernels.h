@@ -937,11 +937,19 @@ __global__ __launch_bounds__(256) void k_scatter(AuxParams a) {
 
 // ------------------------------------------------------------- launchers
 
+// Dynamic LDS that the even-step kernel of FP32/FP64 row-form (walled,
+// mostly fluid) lattices does not use: it caps a CU's 160 KB of LDS at three
+// workgroups, i.e. three waves per SIMD.  Measured on the 256^3 cavity: FP32
+// +1.0% (two waves per SIMD: -2%), FP64 +0.2%, regularized +0.4-0.6%; FP16
+// and the odd step lose with any cap.
+constexpr unsigned kEvenLdsCap = 41u << 10;
+
 template <int Q, int P, int MS, bool TG, int MODE, bool ROWS>
 static hipError_t launch_step_rows(const StepParams &p, int parity, hipStream_t s) {
     const dim3 grid(8 * p.tiles_per_xcd), block(256);
+    constexpr unsigned lds_even = (ROWS && TG && P != 2) ? kEvenLdsCap : 0u;
     if (parity == 0)
-        k_collide_stream<Q, P, MS, TG, MODE, 0, ROWS><<<grid, block, 0, s>>>(p);
+        k_collide_stream<Q, P, MS, TG, MODE, 0, ROWS><<<grid, block, lds_even, s>>>(p);
     else
         k_collide_stream<Q, P, MS, TG, MODE, 1, ROWS><<<grid, block, 0, s>>>(p);
     return hipGetLastError();
