@@ -261,7 +261,9 @@ F16S, F32, F64 = lbm.LBM_F16S, lbm.LBM_F32, lbm.LBM_F64
     (F16S, 19, 64, 21, 9, "walls"), (F16S, 27, 128, 10, 7, "walls"), (F16S, 19, 4096, 3, 2, "walls"),
     (F16S, 19, 64, 5, 11, "periodic"), (F16S, 27, 128, 9, 4, "periodic"), (F16S, 19, 256, 6, 5, "cavity"),
     (F32, 19, 64, 21, 9, "walls"), (F32, 27, 128, 10, 7, "walls"), (F32, 19, 256, 12, 10, "cavity"),
-    (F64, 19, 64, 21, 9, "walls"), (F64, 27, 256, 12, 10, "cavity"), (F32, 19, 64, 21, 9, "sparse")])
+    (F64, 19, 64, 21, 9, "walls"), (F64, 27, 256, 12, 10, "cavity"), (F32, 19, 64, 21, 9, "sparse"),
+    (F64, 19, 64, 6, 8, "open"), (F16S, 27, 64, 6, 8, "open"),
+    (F64, 19, 128, 9, 7, "mixed"), (F16S, 27, 64, 9, 7, "mixed")])
 def test_row_form_matches_node_form(prec, q, nx, ny, nz, kind):
     if kind in ("walls", "sparse"):
         # "sparse": mostly solid, where FP32/FP64 keep the node form
@@ -272,6 +274,16 @@ def test_row_form_matches_node_form(prec, q, nx, ny, nz, kind):
         # D3Q27: the Smagorinsky model with a body force; D3Q19: plain BGK
         tags = inputs.all_fluid(nx, ny, nz, tag=inputs.TAG_SMAG if q == 27 else inputs.TAG_BGK)
         kw = dict(tau=0.52, smag_cs=0.1, force=(1e-5, 0, 0)) if q == 27 else dict(tau=0.7)
+    elif kind == "open":
+        # velocity inlet / pressure outlet on the x planes of a walled channel
+        tags = _open_channel(nx, ny, nz, inputs.TAG_TRT)
+        kw = dict(tau=0.7, bc_velocity=(0.03, 0, 0), bc_density=(1.0, 1.0))
+    elif kind == "mixed":
+        # every model in one lattice (the all-model kernel), walls and a force
+        tags = inputs.random_tags(nx, ny, nz, seed=31, solid_frac=0.08, wall_frac=0.03,
+                                  fluid_tags=(inputs.TAG_BGK, inputs.TAG_TRT, inputs.TAG_SMAG,
+                                              inputs.TAG_REG, inputs.TAG_RR))
+        kw = dict(tau=0.7, smag_cs=0.1, force=(1e-5, 0, 0), wall_velocity=[(0.05, 0, 0), (0, 0.02, 0)])
     else:
         tags = _box_cavity(nx, ny, nz)
         kw = dict(tau=0.6, wall_velocity=[(0.1, 0, 0)])
