@@ -181,8 +181,9 @@ void lbm_destroy(lbm_lattice *lat);
 
 /* Override the launch geometry: 256-thread blocks updating tiles of tx x ty
  * nodes of one z-plane, one node per thread (tx in {32,64,128,256},
- * tx*ty == 256).  Results are bitwise independent of the choice; this exists
- * for tuning and for that test.  The shape also decides whether a lattice
+ * tx*ty == 256).  Populations are bitwise independent of the choice (the FP64
+ * reductions sum per-tile partials, so their rounding follows the tile
+ * shape); this exists for tuning and for that test.  The shape also decides whether a lattice
  * whose nx is a power of two in [64, 4096] uses row-form addressing (tx >= 64;
  * FP16 storage, or a tagged lattice with at least half of its nodes fluid; the
  * variant name then ends in "/rows").  EINVAL for other shapes. */
