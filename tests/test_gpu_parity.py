@@ -312,6 +312,31 @@ def test_row_form_matches_node_form(prec, q, nx, ny, nz, kind):
                 assert np.allclose(a[k], b[k], rtol=1e-12, atol=1e-10), k
 
 
+
+def test_row_form_full_size_tgv512_f16():
+    """The 512^3 D3Q27 Taylor-Green lattice in FP16 storage (3.6e9 population
+    elements, past 2^31): row form (default tiles) and node form (32-wide tiles)
+    give bitwise-equal populations after an even and an odd step, on sampled
+    nodes that include the periodic faces and the last block of the array."""
+    tags, kw, rho, u, _ = _bench_workload("tgv512_d3q27_smag")
+    nz, ny, nx = tags.shape
+    rng = np.random.default_rng(11)
+    faces = [((z * ny + y) * nx + x) for z in (0, nz - 1) for y in (0, 17, ny - 1) for x in range(nx)]
+    tail = list(range(nx * ny * nz - 5000, nx * ny * nz))
+    cells = np.unique(np.concatenate([faces, tail, rng.choice(nx * ny * nz, 20000, replace=False)]))
+    outs, names = [], []
+    for tx in (256, 32):
+        L = lbm.Lattice(tags, prec=lbm.LBM_F16S, **kw)
+        L.set_launch(tx, 256 // tx)
+        names.append(L.variant)
+        L.init_equilibrium(rho, u)
+        L.step(2)
+        outs.append(L.read_cells(cells))
+        L.close()
+    _print("tgv512 f16", names, cells.size)
+    assert names[0].endswith("/rows") and not names[1].endswith("/rows")
+    assert np.array_equal(outs[0], outs[1])
+
 def _box_cavity(nx, ny, nz):
     """Walls on all six faces, a moving lid (tag 16) on the top plane."""
     t = np.ones((nz, ny, nx), np.uint8)
