@@ -107,9 +107,11 @@ def infer_deployed(P, X, nu0):
     return np.array([mlp_eddy_viscosity(P, row, nu0) for row in np.asarray(X, np.float64)])
 
 
-def box_filter_targets(rho, u, factor, nu_c):
-    """Training features (n_coarse x 7) and targets nu_t / nu_c from fine fields
-    rho[nz,ny,nx], u[3,nz,ny,nx]; coarse order (Z, Y, X) with X fastest."""
+def favre_filter(rho, u, factor):
+    """Box filter over factor^3 fine blocks: coarse density <rho> (block mean),
+    Favre velocity U = <rho u>/<rho> and subgrid stress
+    T_ab = <rho u_a u_b>/<rho> - U_a U_b (density-weighted, so that T is the
+    block's mass-weighted velocity covariance)."""
     nz, ny, nx = rho.shape
     f = factor
     cz, cy, cx = nz // f, ny // f, nx // f
@@ -123,24 +125,51 @@ def box_filter_targets(rho, u, factor, nu_c):
     for a in range(3):
         for b in range(3):
             T[a, b] = blocks(rho * u[a] * u[b]) / sr - U[a] * U[b]
-    rbar = sr / f ** 3
+    return sr / f ** 3, np.stack(U), T
+
+
+def central_strain(U):
+    """Resolved strain S_ab = (dU_a/dx_b + dU_b/dx_a)/2 of a coarse field
+    U[3][Z][Y][X] by second-order central differences on the periodic grid."""
     # G[a][b] = dU_b/dx_a; axis of x_a in the (Z, Y, X) array is 2 - a
-    G = np.empty((3, 3) + sr.shape)
+    G = np.empty((3, 3) + U.shape[1:])
     for a in range(3):
         ax = 2 - a
         for b in range(3):
             G[a, b] = 0.5 * (np.roll(U[b], -1, axis=ax) - np.roll(U[b], 1, axis=ax))
-    S = 0.5 * (G + G.transpose(1, 0, 2, 3, 4))
+    return 0.5 * (G + G.transpose(1, 0, 2, 3, 4))
+
+
+def eddy_viscosity_target(T, S):
+    """Least-squares eddy viscosity of the deviatoric subgrid stress on the
+    form -2 nu_t S, clipped at zero: nu_t = max(0, -dev(T):S / (2 S:S + 1e-30))."""
     trT = (T[0, 0] + T[1, 1] + T[2, 2]) / 3.0
     Td = T - np.eye(3)[:, :, None, None, None] * trT
     num = np.einsum("ab...,ab...->...", Td, S)
     ss = np.einsum("ab...,ab...->...", S, S)
-    nut = np.maximum(0.0, -num / (2.0 * ss + 1e-30))
+    return np.maximum(0.0, -num / (2.0 * ss + 1e-30))
+
+
+def closure_features(S, rbar, nut, nu_c):
+    """Features of each coarse node (n x 7): the non-equilibrium momentum flux
+    Pi = -2 rho c_s^2 tau_e S (first-order Chapman-Enskog, c_s^2 = 1/3) a
+    coarse lattice relaxing with tau_e = 3 (nu_c + nu_t) + 1/2 carries, in the
+    order xx, yy, zz, xy, xz, yz, then <rho>."""
     tau_e = 3.0 * (nu_c + nut) + 0.5
     c = -2.0 / 3.0 * rbar * tau_e
-    feat = np.stack([c * S[0, 0], c * S[1, 1], c * S[2, 2], c * S[0, 1], c * S[0, 2], c * S[1, 2], rbar],
+    return np.stack([c * S[0, 0], c * S[1, 1], c * S[2, 2], c * S[0, 1], c * S[0, 2], c * S[1, 2], rbar],
                     axis=-1).reshape(-1, 7)
-    return feat, (nut / nu_c).reshape(-1), {"T": T, "S": S, "U": np.stack(U), "rho": rbar}
+
+
+def box_filter_targets(rho, u, factor, nu_c):
+    """Training features (n_coarse x 7) and targets nu_t / nu_c from fine fields
+    rho[nz,ny,nx], u[3,nz,ny,nx]; coarse order (Z, Y, X) with X fastest.
+    The four steps above in order: filter, strain, target, features."""
+    rbar, U, T = favre_filter(rho, u, factor)
+    S = central_strain(U)
+    nut = eddy_viscosity_target(T, S)
+    feat = closure_features(S, rbar, nut, nu_c)
+    return feat, (nut / nu_c).reshape(-1), {"T": T, "S": S, "U": U, "rho": rbar}
 
 
 def bf16_array(a):

@@ -141,3 +141,113 @@ def test_filter_subgrid_variance_and_strain():
     expect = 0.5 * s * np.cos(k * Z) * np.sin(k)
     assert np.allclose(aux2["S"][0, 2][:, 0, 0], expect, atol=1e-15)
     assert np.allclose(aux2["S"][2, 0], aux2["S"][0, 2])
+
+
+def test_favre_filter_weights_by_density():
+    """One 2^3 block pattern with rho = 1 + a s, u_x = U0 + b s, u_y = V0 + c s
+    (s = +1 on the block's low-x half, -1 on the other): the density-weighted
+    means are U_x = U0 + a b, U_y = V0 + a c and the covariances
+    T_xx = b^2 (1 - a^2), T_xy = b c (1 - a^2), T_yy = c^2 (1 - a^2), worked by
+    hand (a plain block mean would give U_x = U0 and T_xx = b^2)."""
+    f, n = 2, 4
+    a, b, c, U0, V0 = 0.5, 0.1, -0.04, 0.2, 0.03
+    x = np.arange(n)[None, None, :] * np.ones((n, n, n))
+    s = np.where(x % f == 0, 1.0, -1.0)
+    rho = 1.0 + a * s
+    u = np.zeros((3, n, n, n))
+    u[0] = U0 + b * s
+    u[1] = V0 + c * s
+    rbar, U, T = om.favre_filter(rho, u, f)
+    assert np.allclose(rbar, 1.0, rtol=0, atol=1e-15)
+    assert np.allclose(U[0], 0.25, rtol=0, atol=1e-15)
+    assert np.allclose(U[1], 0.01, rtol=0, atol=1e-15)
+    assert np.allclose(U[2], 0.0, rtol=0, atol=1e-15)
+    assert np.allclose(T[0, 0], 0.0075, rtol=0, atol=1e-15)
+    assert np.allclose(T[0, 1], -0.003, rtol=0, atol=1e-15)
+    assert np.allclose(T[1, 0], -0.003, rtol=0, atol=1e-15)
+    assert np.allclose(T[1, 1], 0.0012, rtol=0, atol=1e-15)
+    assert np.abs(T[2]).max() < 1e-15
+    # the full pipeline passes the same filter through
+    _, _, aux = om.box_filter_targets(rho, u, f, 0.01)
+    assert np.allclose(aux["U"][0], 0.25, rtol=0, atol=1e-15)
+
+
+def _fine_field_with_stress(Uc, Tc, f):
+    """Fine velocity whose factor-f box filter (rho = 1) has coarse mean Uc[3][Z][Y][X]
+    and subgrid stress Tc[3][3][Z][Y][X]: each fine node carries Uc + L s with
+    L L^T = Tc (Cholesky) and s_a = +1 on the block's low half along axis a, -1 on
+    the high half; the eight sign patterns are orthogonal with mean zero, so the
+    block covariance is L I L^T = Tc."""
+    cz, cy, cx = Uc.shape[1:]
+    nz, ny, nx = cz * f, cy * f, cx * f
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    sgn = np.stack([np.where(x % f < f // 2, 1.0, -1.0), np.where(y % f < f // 2, 1.0, -1.0),
+                    np.where(z % f < f // 2, 1.0, -1.0)])
+    Tm = np.moveaxis(Tc, (0, 1), (-2, -1))          # [Z][Y][X][3][3]
+    Lc = np.linalg.cholesky(Tm)
+    Lf = Lc[z // f, y // f, x // f]                  # [nz][ny][nx][3][3]
+    v = np.einsum("...ab,b...->a...", Lf, sgn)
+    return Uc[:, z // f, y // f, x // f] + v
+
+
+@pytest.mark.parametrize("kind", ["shear", "axial"])
+def test_eddy_viscosity_target_of_known_stress(kind):
+    """Coarse flows with the closed-form discrete strain of a sine (pinned above)
+    and a subgrid stress T = -2 nu S + alpha I built into the fine field.  The
+    least-squares target of dev(T) on -2 nu_t S is nu for a traceless shear, and
+    (2/3) nu for the axial strain S = diag(s, 0, 0) (dev(S):S = (2/3) s^2), in
+    either case independent of alpha; a backscattering stress T = +2 nu S + alpha I
+    gives 0 (clipped)."""
+    f, nc, s, nu = 2, 8, 0.02, 3e-3
+    k = 2 * np.pi / nc
+    Z = np.arange(nc)
+    Uc = np.zeros((3, nc, nc, nc))
+    S = np.zeros((3, 3, nc, nc, nc))
+    if kind == "shear":
+        Uc[0] = (s * np.sin(k * Z))[:, None, None]
+        S[0, 2] = S[2, 0] = (0.5 * s * np.cos(k * Z) * np.sin(k))[:, None, None]
+        expect = nu
+    else:
+        Uc[0] = (s * np.sin(k * Z))[None, None, :]
+        S[0, 0] = (s * np.cos(k * Z) * np.sin(k))[None, None, :]
+        expect = 2.0 / 3.0 * nu
+    live = np.einsum("ab...,ab...->...", S, S) > 1e-20
+    smax = np.abs(S).max()
+    for alpha_mult in (3.0, 40.0):
+        alpha = alpha_mult * 2 * nu * smax
+        for sign, want in ((-1.0, expect), (1.0, 0.0)):
+            T = sign * 2 * nu * S + alpha * np.eye(3)[:, :, None, None, None]
+            u = _fine_field_with_stress(Uc, T, f)
+            feat, tgt, aux = om.box_filter_targets(np.ones((nc * f,) * 3), u, f, 1.0)
+            assert np.allclose(aux["T"], T, rtol=0, atol=1e-14)
+            assert np.allclose(aux["S"], S, rtol=0, atol=1e-15)
+            nut = tgt.reshape(nc, nc, nc)
+            assert np.allclose(nut[live], want, rtol=1e-9, atol=0)
+
+
+@pytest.mark.parametrize("tau", [0.62, 1.3])
+def test_features_equal_couette_nonequilibrium_flux(tau):
+    """The feature formula Pi = -2 rho c_s^2 tau_e S against a lattice that carries
+    it: the oracle's steady BGK Couette flow at tau = tau_e (linear profile, exact
+    for this flow).  Pi^neq_xz measured from its populations, sum c_x c_z (f - f^eq),
+    equals the xz feature computed from the flow's own density and central-difference
+    strain, with nu_c + nu_t = (tau - 1/2)/3 split between the two."""
+    nz, U = 14, 0.02
+    tags = inputs.channel_tags(1, 1, nz, top=inputs.TAG_WALL0)
+    o = oracle.Oracle(1, 1, nz, q=19, tau=tau, tags=tags, wall_velocity=[(U, 0, 0)])
+    o.init_equilibrium()
+    o.run(20000)
+    rho, u = o.fields()
+    c, _, _ = oracle.tables(19)
+    nu_tot = (tau - 0.5) / 3.0
+    for z in (3, 7, 10):
+        fz = o.f[:, z, 0, 0]
+        feq = oracle.equilibrium(19, rho[z, 0, 0], u[:, z, 0, 0])
+        pi_xz = float(np.sum(c[:, 0] * c[:, 2] * (fz - feq)))
+        S = np.zeros((3, 3, 1, 1, 1))
+        S[0, 2] = S[2, 0] = 0.25 * (u[0, z + 1, 0, 0] - u[0, z - 1, 0, 0])
+        feat = om.closure_features(S, np.full((1, 1, 1), rho[z, 0, 0]), np.full((1, 1, 1), 0.6 * nu_tot),
+                                   0.4 * nu_tot)
+        assert abs(feat[0, 4] / pi_xz - 1.0) < 1e-9
+        assert feat[0, 6] == rho[z, 0, 0]
+        assert np.all(feat[0, [0, 1, 2, 3, 5]] == 0.0)
