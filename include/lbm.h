@@ -118,7 +118,7 @@ typedef struct {
     int32_t nx, ny, nz;    /* lattice size, each >= 1, nx*ny*nz < 2^31          */
     int32_t q;             /* lbm_q                                              */
     int32_t prec;          /* lbm_prec                                           */
-    int32_t flags;         /* reserved, must be 0                                */
+    int32_t flags;         /* 0, or LBM_FLAG_FREE_STREAM                         */
     double rho0;           /* reference density (offset and wall density), > 0  */
     double tau;            /* relaxation time, tau = 3 nu + 1/2, must be > 1/2  */
     double trt_lambda;     /* TRT magic parameter (3/16 for exact walls), > 0   */
@@ -129,6 +129,13 @@ typedef struct {
     double bc_density[2];  /* density of pressure-boundary nodes (> 0): [0] on
                               x = 0 (tag 8), [1] on x = nx-1 (tag 7)          */
 } lbm_config;
+
+/* lbm_config.flags: collision switched off on every fluid node (the
+ * post-collision populations equal the pre-collision ones), so a step is pure
+ * streaming with the same bounce-back and moving-wall terms.  For checking
+ * the streaming maps and for timing the memory access pattern of the step
+ * without its arithmetic; not a physical model. */
+#define LBM_FLAG_FREE_STREAM 1
 
 /* FP64 domain reductions of the natural state at time `step`, over fluid nodes. */
 typedef struct {
@@ -213,8 +220,12 @@ lbm_status lbm_step(lbm_lattice *lat, int64_t n_steps);
 lbm_status lbm_step_reduce(lbm_lattice *lat, int64_t n_steps, int64_t every, lbm_moments *series,
                            int64_t n_series);
 
-/* Reductions of the current state (a standalone pass).  Synchronizes.
- * EUNSTABLE if non-finite values were found. */
+/* Reductions of the current state (a standalone pass): the domain sums of
+ * Sec. 2.2 ("Reductions", the transform_reduce of every node's moments) with
+ * the kinetic energy of Eq. (5); fields as in lbm_moments, FP64 per node,
+ * summed in a fixed order (run-to-run deterministic for a fixed launch
+ * shape).  out: host, one lbm_moments.  Synchronizes.  EINVAL for a null
+ * out; EUNSTABLE if non-finite values were found (out still filled). */
 lbm_status lbm_reduce(lbm_lattice *lat, lbm_moments *out);
 
 /* Volume-averaged enstrophy of the natural state (Eq. 5, second part):
@@ -234,9 +245,18 @@ int64_t lbm_time(const lbm_lattice *lat);
 
 /* ------------------------------------------------------------- readback */
 
+/* Readback and checkpoint calls.  They play the part of the paper's bridge
+ * between the GPU container and the host (Sec. 2.1: data copied between the
+ * two containers at run time, on a per-need basis, for pre- and
+ * post-processing; Sec. 2.3, Fig. 4: hybrid execution) and of its
+ * serialized checkpoints (Sec. 2.3).  Each one gathers or scatters on the
+ * device in chunks of whole z-planes (at most ~256 MB of FP64 staging) and
+ * copies through host memory the caller owns. */
+
 /* Density and velocity of the natural state at the current time, FP64:
  * rho_host nx*ny*nz, u_host 3*nx*ny*nz (planes ux, uy, uz), each nullable.
- * u = (sum c_i f_i + F/2)/rho.  Non-fluid nodes read 0.  Synchronizes. */
+ * u = (sum c_i f_i + F/2)/rho.  Non-fluid nodes read 0.  Synchronizes.
+ * ENOMEM if the host staging copy cannot be allocated. */
 lbm_status lbm_read_fields(lbm_lattice *lat, double *rho_host, double *u_host);
 
 /* All populations f_i (offset added back, FP64, canonical order, natural
@@ -315,9 +335,54 @@ lbm_status lbm_mlp_train(float *params_dev, const float *feat_dev, const float *
                          const int64_t *perm_dev, int batch, int epochs, double lr,
                          float *loss_log_dev, void *hip_stream);
 
+/* ------------------------------------------------ slab faces (Sec. 2.2, 2.3) */
+
+/* Populations of one node that cross a z face of a slab: 5 (D3Q19) or 9
+ * (D3Q27), the directions with c_z = +1 (face 0) or c_z = -1 (face 1) in
+ * canonical order.  Returns 0 for a bad q. */
+int lbm_face_populations(int q);
+
+/* Pack (unpack) the slots that cross a z face: the paper packs the data
+ * exchanged between blocks on the device before the GPU-to-GPU transfer and
+ * unpacks it there after (Sec. 2.2 "Prefix Sums"; Sec. 2.3 "GPU-GPU
+ * communication using pinned memory and MPI").
+ *   face 0: the z = 0 plane, slots of the directions with c_z = +1;
+ *   face 1: the z = nz-1 plane, slots of the directions with c_z = -1.
+ * buf_dev: device memory of lbm_face_populations(q)*nx*ny elements of the
+ * storage type (8, 4 or 2 bytes: the stored bits are copied unchanged),
+ * element [j][y][x] = the raw slot of the j-th such direction of node
+ * (x, y) of the plane; the caller owns it.  Asynchronous on the lattice's
+ * stream.  EINVAL for a bad face or null buffer.
+ *
+ * Slab decomposition with the in-place AA scheme.  Slabs S_0 .. S_{m-1}
+ * stacked along z (each its own lattice of nz_j planes, same nx, ny, every
+ * fluid node one model: lbm_create of an all-fluid single-model tag array;
+ * masks across slab faces are not built) advance the stacked lattice,
+ * periodic in z, exactly: even steps (lbm_time even) need nothing; around
+ * each odd step,
+ *   before: S_j.face0 <- S_{j+1}.face0 and S_j.face1 <- S_{j-1}.face1,
+ *   after : S_{j+1}.face0 <- S_j.face0 and S_{j-1}.face1 <- S_j.face1
+ * (indices mod m; pack all, then unpack all).  Each slab's own periodic
+ * wrap then lands every crossing access on the neighbour's values. */
+lbm_status lbm_face_pack(lbm_lattice *lat, int face, void *buf_dev);
+lbm_status lbm_face_unpack(lbm_lattice *lat, int face, const void *buf_dev);
+
 /* -------------------------------------------------------------- utilities */
 
-/* Velocity i of the canonical order of lattice q: returns the opposite index
+/* Memory-bandwidth probe (a measured HBM ceiling, not part of the method):
+ * kind 0 copies src_dev to dst_dev, kind 1 reads src_dev (one word per
+ * 1024 vectors is written to dst_dev only if the sum of what was read equals
+ * a fixed constant, which keeps the loads live), kind 2 fills dst_dev; each
+ * lane moves lane_bytes (4, 8 or 16) per access, four accesses per lane.
+ * dst_dev and src_dev: device buffers of `bytes` bytes (src_dev unused by
+ * kind 2), bytes a positive multiple of 4096 * lane_bytes.  Asynchronous on
+ * hip_stream.  EINVAL otherwise. */
+lbm_status lbm_probe_bandwidth(int kind, void *dst_dev, const void *src_dev, size_t bytes, int lane_bytes,
+                               void *hip_stream);
+
+
+/* Velocity i of the canonical order of lattice q (the lattice descriptor of
+ * Sec. 2.1: number of populations and lattice connectivity): returns the opposite index
  * and fills c[3] and the weight w; -1 for a bad (q, i).  Order: rest;
  * +x,+y,+z; (1,1,0),(1,-1,0),(1,0,1),(1,0,-1),(0,1,1),(0,1,-1); for D3Q27
  * (1,1,1),(1,1,-1),(1,-1,1),(1,-1,-1); then the negatives in the same order

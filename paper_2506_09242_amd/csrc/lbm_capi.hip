@@ -18,19 +18,18 @@
 using namespace lbmd;
 
 // ------------------------------------------------------------------ errors
-static thread_local std::string g_err;
+// A fixed buffer per thread: recording an error allocates nothing.
+static thread_local char g_err[512];
 
 static lbm_status set_err(lbm_status s, const char *fmt, ...) {
-    char buf[512];
     va_list ap;
     va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
     va_end(ap);
-    g_err = buf;
     return s;
 }
 
-extern "C" const char *lbm_last_error(void) { return g_err.c_str(); }
+extern "C" const char *lbm_last_error(void) { return g_err; }
 
 // ------------------------------------------------------------------ lattice
 struct lbm_lattice {
@@ -90,11 +89,12 @@ struct Launchers {
     hipError_t (*init)(const AuxParams &, hipStream_t);
     hipError_t (*gather)(const AuxParams &, int, hipStream_t);
     hipError_t (*scatter)(const AuxParams &, hipStream_t);
+    hipError_t (*face)(const AuxParams &, int, int, void *, hipStream_t);
 };
 
 template <int Q, int P>
 Launchers make_launchers() {
-    return {&launch_step<Q, P>, &launch_init<Q, P>, &launch_gather<Q, P>, &launch_scatter<Q, P>};
+    return {&launch_step<Q, P>, &launch_init<Q, P>, &launch_gather<Q, P>, &launch_scatter<Q, P>, &launch_face<Q, P>};
 }
 
 Launchers pick(int q, int prec) {
@@ -141,7 +141,7 @@ lbm_status validate(const lbm_config *c) {
     if (n >= (1LL << 31)) return set_err(LBM_EINVAL, "nx*ny*nz = %lld exceeds 2^31 - 1", n);
     if (c->q != 19 && c->q != 27) return set_err(LBM_EINVAL, "q must be 19 or 27 (got %d)", c->q);
     if (c->prec < 0 || c->prec > 2) return set_err(LBM_EINVAL, "unknown precision %d", c->prec);
-    if (c->flags != 0) return set_err(LBM_EINVAL, "flags must be 0");
+    if ((c->flags & ~LBM_FLAG_FREE_STREAM) != 0) return set_err(LBM_EINVAL, "unknown flags 0x%x", c->flags);
     if (!(c->rho0 > 0.0) || !std::isfinite(c->rho0)) return set_err(LBM_EINVAL, "rho0 must be > 0");
     if (!(c->tau > 0.5) || !std::isfinite(c->tau)) return set_err(LBM_EINVAL, "tau must be > 1/2 (got %g)", c->tau);
     if (!(c->trt_lambda > 0.0) || !std::isfinite(c->trt_lambda)) return set_err(LBM_EINVAL, "trt_lambda must be > 0");
@@ -231,12 +231,12 @@ StepParams step_params(const lbm_lattice *L) {
 // step kernels use row-form addressing (depends on the tile shape).
 void name_variant(lbm_lattice *L) {
     static const char *msname[] = {"bgk", "trt", "reg", "rr", "bgk+smag", "trt+open", "bgk+smag+mlp", "all"};
-    int msi = 0;
+    const char *ms = "stream";
     for (int k = 0; k < kNumModelSets; ++k)
-        if (kModelSets[k] == L->ms) msi = k;
+        if (kModelSets[k] == L->ms) ms = msname[k];
     const lbm_config &c = L->cfg;
     snprintf(L->variant, sizeof L->variant, "D3Q%d/%s/%s/%s%s", c.q,
-             c.prec == LBM_F64 ? "f64" : (c.prec == LBM_F32 ? "f32" : "f16s"), msname[msi],
+             c.prec == LBM_F64 ? "f64" : (c.prec == LBM_F32 ? "f32" : "f16s"), ms,
              L->tagged ? "tagged" : "uniform", step_params(L).row_log2 >= 0 ? "/rows" : "");
 }
 
@@ -451,6 +451,7 @@ static lbm_status create_impl(const lbm_config *cfg, const uint8_t *tags_host, v
             break;
         }
     if (ms < 0) return set_err(LBM_EUNSUPPORTED, "no compiled model set covers the tags");
+    if (cfg->flags & LBM_FLAG_FREE_STREAM) ms = MS_STREAM;
     int n_models = 0, only = LBM_TAG_BGK;
     for (int t = 1; t <= 10; ++t)
         if (hist[t]) {
@@ -879,6 +880,25 @@ static lbm_status scatter_range(lbm_lattice *lat, const double *f_host, int64_t 
     lat->parity = 0;
     lat->t = t;
     return LBM_OK;
+}
+
+extern "C" int lbm_face_populations(int q) { return q == 19 ? 5 : (q == 27 ? 9 : 0); }
+
+static lbm_status face_copy(lbm_lattice *lat, int face, int unpack, void *buf) {
+    CHECK_HANDLE(lat);
+    if (face != 0 && face != 1) return set_err(LBM_EINVAL, "face must be 0 (z = 0) or 1 (z = nz-1)");
+    if (!buf) return set_err(LBM_EINVAL, "null face buffer");
+    AuxParams a = aux_params(lat);
+    HIPCHK(lat, pick(lat->cfg.q, lat->cfg.prec).face(a, face, unpack, buf, lat->stream));
+    return LBM_OK;
+}
+
+extern "C" lbm_status lbm_face_pack(lbm_lattice *lat, int face, void *buf_dev) {
+    return face_copy(lat, face, 0, buf_dev);
+}
+
+extern "C" lbm_status lbm_face_unpack(lbm_lattice *lat, int face, const void *buf_dev) {
+    return face_copy(lat, face, 1, const_cast<void *>(buf_dev));
 }
 
 extern "C" lbm_status lbm_enstrophy(lbm_lattice *lat, double *out) {

@@ -24,6 +24,7 @@ enum ModelSet : int {
     MS_REG = 16,
     MS_OPEN = 32,  // regularized velocity / pressure boundary nodes on the x planes
     MS_RR = 64,    // recursive regularized
+    MS_STREAM = 128,  // no collision (LBM_FLAG_FREE_STREAM): pure streaming
 };
 constexpr int kAllModels = MS_BGK | MS_TRT | MS_SMAG | MS_MLP | MS_REG | MS_OPEN | MS_RR;
 
@@ -123,6 +124,11 @@ template <int Q, int P>
 hipError_t launch_gather(const AuxParams &a, int gmode, hipStream_t s);
 template <int Q, int P>
 hipError_t launch_scatter(const AuxParams &a, hipStream_t s);
+// Copy the slots that cross a z face between the lattice and buf (see
+// lbm_face_pack): face 0 = plane 0, directions with c_z = +1; face 1 =
+// plane nz-1, directions with c_z = -1; unpack = 1 copies buf into the lattice.
+template <int Q, int P>
+hipError_t launch_face(const AuxParams &a, int face, int unpack, void *buf, hipStream_t s);
 
 // Deterministic two-stage sum of the per-tile partials into out[NRED];
 // stage1 holds NRED * kFinalizeBlocks doubles.

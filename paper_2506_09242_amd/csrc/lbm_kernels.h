@@ -302,6 +302,11 @@ __device__ __forceinline__ void collide_regularized(const C (&h)[Q], int tag, co
 // update (collide_regularized); the caller decides where that pays.
 template <int Q, typename C, int MS, bool MOM = false>
 __device__ __forceinline__ void collide_node(const C (&h)[Q], int tag, bool live, const StepParams &p, C (&hs)[Q]) {
+    if constexpr (MS == MS_STREAM) {
+        // collision switched off: the step only streams (and bounces back)
+        sfor<Q>([&](auto I) { hs[decltype(I)::value] = h[decltype(I)::value]; });
+        return;
+    }
     if constexpr (MOM && (MS == MS_REG || MS == MS_RR)) {
         collide_regularized<Q, C, MS>(h, tag, p, hs);
         return;
@@ -935,6 +940,36 @@ __global__ __launch_bounds__(256) void k_scatter(AuxParams a) {
     });
 }
 
+// Slab-face copy: one thread per node of the plane; each copies the slots of
+// the directions crossing the face (c_z = +1 on face 0, c_z = -1 on face 1),
+// the j-th of them to buf[j][y][x].  Coalesced along x on both sides.
+template <int Q, int P>
+__global__ __launch_bounds__(256) void k_face(AuxParams a, int face, int unpack, void *buf) {
+    using S = typename Prec<P>::S;
+    const long long nxy = (long long)a.nx * a.ny;
+    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= nxy) return;
+    const int plane = face == 0 ? 0 : a.nz - 1;
+    const int n = (int)((long long)plane * nxy + t);
+    S *f = static_cast<S *>(a.pops);
+    S *b = static_cast<S *>(buf);
+    const long long base = pop_base<Q>(n);
+    const int cz = face == 0 ? 1 : -1;
+    int j = 0;
+    sfor<Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        if constexpr (V<Q, i>::z != 0) {
+            if (V<Q, i>::z == cz) {
+                S *slot = f + base + slot_off(i);
+                S *e = b + (long long)j * nxy + t;
+                if (unpack) *slot = *e;
+                else *e = *slot;
+                ++j;
+            }
+        }
+    });
+}
+
 // ------------------------------------------------------------- launchers
 
 // Dynamic LDS that the even-step kernel of FP32/FP64 row-form (walled,
@@ -997,6 +1032,7 @@ hipError_t launch_step(const StepParams &p, int ms, bool tagged, int mode, int p
         case MS_TRT | MS_OPEN: return launch_step_geo<Q, P, MS_TRT | MS_OPEN>(p, tagged, mode, parity, s);
         case MS_RR: return launch_step_geo<Q, P, MS_RR>(p, tagged, mode, parity, s);
         case kAllModels: return launch_step_geo<Q, P, kAllModels>(p, tagged, mode, parity, s);
+        case MS_STREAM: return launch_step_geo<Q, P, MS_STREAM>(p, tagged, mode, parity, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -1030,10 +1066,18 @@ hipError_t launch_scatter(const AuxParams &a, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <int Q, int P>
+hipError_t launch_face(const AuxParams &a, int face, int unpack, void *buf, hipStream_t s) {
+    const long long nxy = (long long)a.nx * a.ny;
+    k_face<Q, P><<<(unsigned)((nxy + 255) / 256), 256, 0, s>>>(a, face, unpack, buf);
+    return hipGetLastError();
+}
+
 #define LBMD_INSTANTIATE(Q, P)                                                                           \
     template hipError_t launch_step<Q, P>(const StepParams &, int, bool, int, int, hipStream_t);          \
     template hipError_t launch_init<Q, P>(const AuxParams &, hipStream_t);                                \
     template hipError_t launch_gather<Q, P>(const AuxParams &, int, hipStream_t);                         \
-    template hipError_t launch_scatter<Q, P>(const AuxParams &, hipStream_t);
+    template hipError_t launch_scatter<Q, P>(const AuxParams &, hipStream_t);                             \
+    template hipError_t launch_face<Q, P>(const AuxParams &, int, int, void *, hipStream_t);
 
 }  // namespace lbmd

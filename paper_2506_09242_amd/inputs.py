@@ -139,13 +139,16 @@ def tgv3d_fields(n: int, u0: float, rho0: float = 1.0):
     x_i = 2 pi i / n.  Pressure term read as rho0 u0^2/16 (dimensionally
     required); density from the lattice equation of state p = rho / 3."""
     s = 2 * np.pi * np.arange(n) / n
-    z, y, x = np.meshgrid(s, s, s, indexing="ij")
-    ux = u0 * np.sin(x) * np.cos(y) * np.cos(z)
-    uy = -u0 * np.cos(x) * np.sin(y) * np.cos(z)
-    uz = np.zeros_like(ux)
+    # separable factors broadcast over (z, y, x); products in the same order as
+    # the formulas, so the values do not depend on this arrangement
+    x, y, z = s[None, None, :], s[None, :, None], s[:, None, None]
+    u = np.empty((3, n, n, n))
+    u[0] = u0 * np.sin(x) * np.cos(y) * np.cos(z)
+    u[1] = -u0 * np.cos(x) * np.sin(y) * np.cos(z)
+    u[2] = 0.0
     dp = rho0 * u0 * u0 / 16.0 * (np.cos(2 * z) + 2.0) * (np.cos(2 * x) + np.cos(2 * y))
     rho = rho0 + 3.0 * dp
-    return rho, np.stack([ux, uy, uz])
+    return rho, u
 
 
 def tgv2d_fields(n: int, nz: int, u0: float, rho0: float = 1.0):

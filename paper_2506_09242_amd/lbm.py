@@ -27,6 +27,7 @@ TAG_RR = 10
 MLP_NPARAMS = 1359
 PREC_NAMES = {"f64": LBM_F64, "f32": LBM_F32, "f16s": LBM_F16S}
 PREC_BYTES = {LBM_F64: 8, LBM_F32: 4, LBM_F16S: 2}
+LBM_FLAG_FREE_STREAM = 1
 
 
 class LbmConfig(C.Structure):
@@ -79,6 +80,10 @@ SIGNATURES = {
     "lbm_velocity": (C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_double)]),
     "lbm_last_error": (C.c_char_p, []),
     "lbm_variant_name": (C.c_char_p, [_P]),
+    "lbm_face_populations": (C.c_int, [C.c_int]),
+    "lbm_face_pack": (C.c_int, [_P, C.c_int, _P]),
+    "lbm_face_unpack": (C.c_int, [_P, C.c_int, _P]),
+    "lbm_probe_bandwidth": (C.c_int, [C.c_int, _P, _P, C.c_size_t, C.c_int, _P]),
 }
 
 _lib = None
@@ -122,11 +127,11 @@ def _dev(t):
 
 def make_config(nx, ny, nz, q=19, prec=LBM_F64, tau=0.8, rho0=1.0, trt_lambda=3.0 / 16.0, smag_cs=0.0,
                 force=(0.0, 0.0, 0.0), wall_velocity: Optional[Sequence] = None, bc_velocity=(0.0, 0.0, 0.0),
-                bc_density=(1.0, 1.0)) -> LbmConfig:
+                bc_density=(1.0, 1.0), flags=0) -> LbmConfig:
     if isinstance(prec, str):
         prec = PREC_NAMES[prec]
     c = LbmConfig()
-    c.nx, c.ny, c.nz, c.q, c.prec, c.flags = nx, ny, nz, q, prec, 0
+    c.nx, c.ny, c.nz, c.q, c.prec, c.flags = nx, ny, nz, q, prec, flags
     c.rho0, c.tau, c.trt_lambda, c.smag_cs = rho0, tau, trt_lambda, smag_cs
     for a in range(3):
         c.force[a] = force[a]
@@ -174,6 +179,15 @@ def lbm_mlp_train(params_dev, feat_dev, target_dev, perm_dev, batch, epochs, lr,
                                _dev(perm_dev), batch, epochs, lr, _dev(loss_log_dev), _stream_handle(stream)))
 
 
+def lbm_face_populations(q) -> int:
+    return lib().lbm_face_populations(int(q))
+
+
+def lbm_probe_bandwidth(kind, dst_dev, src_dev, nbytes, lane_bytes, stream=None):
+    _check(lib().lbm_probe_bandwidth(int(kind), _dev(dst_dev), None if src_dev is None else _dev(src_dev),
+                                     int(nbytes), int(lane_bytes), _stream_handle(stream)))
+
+
 def _stream_handle(stream):
     if stream is None:
         import torch
@@ -192,12 +206,13 @@ class Lattice:
     open-boundary tags (velocity tags 6 and 9; pressure tags 8 on x = 0 and 7 on
     x = nx-1, densities (x = 0, x = nx-1)); stream: a torch stream or raw
     handle (default: torch's current stream); torch_buffer: let torch own the
-    population array (lbm_create_on_buffer).
+    population array (lbm_create_on_buffer); free_stream: collision switched off
+    (LBM_FLAG_FREE_STREAM).
     """
 
     def __init__(self, tags: np.ndarray, q=19, prec=LBM_F64, tau=0.8, rho0=1.0, trt_lambda=3.0 / 16.0,
                  smag_cs=0.0, force=(0.0, 0.0, 0.0), wall_velocity=None, stream=None, torch_buffer=False,
-                 bc_velocity=(0.0, 0.0, 0.0), bc_density=(1.0, 1.0)):
+                 bc_velocity=(0.0, 0.0, 0.0), bc_density=(1.0, 1.0), free_stream=False):
         tags = np.ascontiguousarray(tags, dtype=np.uint8)
         assert tags.ndim == 3
         nz, ny, nx = tags.shape
@@ -205,7 +220,7 @@ class Lattice:
         self.N = nx * ny * nz
         self.q = q
         self.cfg = make_config(nx, ny, nz, q, prec, tau, rho0, trt_lambda, smag_cs, force, wall_velocity,
-                               bc_velocity, bc_density)
+                               bc_velocity, bc_density, LBM_FLAG_FREE_STREAM if free_stream else 0)
         self.tags = tags
         self._stream = _stream_handle(stream)
         self._buf = None
@@ -325,3 +340,10 @@ class Lattice:
 
     def filter_snapshot(self, factor, feat_dev, target_dev):
         _check(lib().lbm_filter_snapshot(self.h, int(factor), _dev(feat_dev), _dev(target_dev)))
+
+    def face_pack(self, face, buf_dev):
+        """Copy the slots crossing z face `face` (0: plane 0, 1: plane nz-1) into buf_dev."""
+        _check(lib().lbm_face_pack(self.h, int(face), _dev(buf_dev)))
+
+    def face_unpack(self, face, buf_dev):
+        _check(lib().lbm_face_unpack(self.h, int(face), _dev(buf_dev)))

@@ -38,3 +38,15 @@ def max_abs_pop_error(f_gpu, f_orc, tags):
 
 def rel_l2(a, b):
     return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def momentum_bound(f_gpu, f_orc, tags, q):
+    """Largest difference two domain momentum sums can show when their node
+    populations differ by f_gpu - f_orc: |dP_a| <= sum over fluid nodes and i of
+    |c_ia| |df_i| (triangle inequality), plus the rounding of two sums of the
+    same terms (64 unit roundoffs of sum |c_ia| f_i).  Per axis a."""
+    m = fluid_mask(tags)
+    c = np.array([lbm.lbm_velocity(q, i)[0] for i in range(q)], dtype=np.float64)  # [q][3]
+    d = np.abs(f_gpu[:, m] - f_orc[:, m]).sum(axis=1)      # [q]
+    s = np.abs(f_orc[:, m]).sum(axis=1)                    # [q]
+    return np.abs(c).T @ d + 64 * 2.0 ** -53 * (np.abs(c).T @ s)

@@ -71,7 +71,7 @@ def _create(cfg, tags):
 @pytest.mark.parametrize("field,value,needle", [
     ("tau", 0.5, "tau"), ("tau", 0.3, "tau"), ("q", 15, "q must"), ("prec", 7, "precision"),
     ("rho0", 0.0, "rho0"), ("trt_lambda", -1.0, "trt_lambda"), ("smag_cs", -0.1, "smag_cs"),
-    ("flags", 1, "flags"), ("nx", 0, "size"),
+    ("flags", 2, "flags"), ("flags", -1, "flags"), ("nx", 0, "size"),
 ])
 def test_create_rejects_bad_config(field, value, needle):
     cfg = lbm.make_config(4, 4, 4)
@@ -131,6 +131,23 @@ def test_null_handles_are_rejected():
     assert L.lbm_set_launch(None, 64, 4) == lbm.LBM_EINVAL
     L.lbm_destroy(None)  # no-op
     assert L.lbm_time(None) == -1
+
+
+def test_face_and_probe_argument_validation():
+    L = lbm.lib()
+    assert L.lbm_face_populations(19) == 5 and L.lbm_face_populations(27) == 9
+    assert L.lbm_face_populations(0) == 0
+    assert L.lbm_face_pack(None, 0, None) == lbm.LBM_EINVAL
+    assert L.lbm_face_unpack(None, 1, None) == lbm.LBM_EINVAL
+    # rejected before any device work
+    assert L.lbm_probe_bandwidth(3, None, None, 4096 * 16, 16, None) == lbm.LBM_EINVAL
+    assert "kind" in lbm.lbm_last_error()
+    assert L.lbm_probe_bandwidth(0, None, None, 4096 * 16, 12, None) == lbm.LBM_EINVAL
+    assert "lane_bytes" in lbm.lbm_last_error()
+    assert L.lbm_probe_bandwidth(0, None, None, 4096 * 16 + 4, 16, None) == lbm.LBM_EINVAL
+    assert "multiple" in lbm.lbm_last_error()
+    assert L.lbm_probe_bandwidth(0, None, None, 4096 * 16, 16, None) == lbm.LBM_EINVAL
+    assert "null" in lbm.lbm_last_error()
 
 
 def test_mlp_argument_validation():

@@ -1,0 +1,151 @@
+"""Streaming maps, slab faces and the bandwidth probe on the GPU.
+
+- Free streaming (collision switched off) against the oracle's free streaming:
+  the AA maps, bounce-back and moving-wall terms on their own.
+- Slab decomposition along z with the face pack / unpack kernels (the
+  device-side packing of data exchanged between blocks, Sec. 2.2 "Prefix
+  Sums" and Sec. 2.3 "GPU-GPU communication"): slabs stacked along z that
+  exchange their crossing populations around each odd step reproduce the
+  whole periodic lattice bit for bit.
+- The bandwidth probe copies, reads and writes what it says.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2506_09242_amd import inputs, lbm
+
+from _util import max_rel_pop_error
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    lbm.lib()
+    yield
+
+
+@pytest.mark.parametrize("q", [19, 27])
+@pytest.mark.parametrize("steps", [6, 7])
+def test_free_streaming_matches_oracle(q, steps):
+    """Collision off on both sides: populations translate by c_i, bounce back at
+    walls with the moving-wall term; FP64 within 1e-12, on a walled random
+    lattice and on a periodic one."""
+    nx, ny, nz = 23, 9, 7
+    tags = inputs.random_tags(nx, ny, nz, seed=61, solid_frac=0.2, wall_frac=0.1)
+    rho, u = inputs.random_fields(nx, ny, nz, seed=62)
+    kw = dict(tau=0.8, wall_velocity=[(0.05, 0, 0), (0, -0.03, 0.02)])
+    o = oracle.Oracle(nx, ny, nz, q=q, tags=tags, free_streaming=True, **kw)
+    o.init_equilibrium(rho, u)
+    L = lbm.Lattice(tags, q=q, prec=lbm.LBM_F64, free_stream=True, **kw)
+    assert "/stream/" in L.variant
+    L.init_equilibrium(rho, u)
+    L.step(steps)
+    o.run(steps)
+    assert max_rel_pop_error(L.read_populations(), o.f, tags) <= 1e-12
+    # periodic: after steps, population i of node x is the initial one of x - steps c_i
+    per = inputs.all_fluid(nx, ny, nz)
+    P = lbm.Lattice(per, q=q, prec=lbm.LBM_F64, free_stream=True)
+    P.init_equilibrium(rho, u)
+    f0 = P.read_populations()
+    P.step(steps)
+    f1 = P.read_populations()
+    for i in range(q):
+        c, _, _ = lbm.lbm_velocity(q, i)
+        shifted = np.roll(f0[i], shift=(steps * c[2], steps * c[1], steps * c[0]), axis=(0, 1, 2))
+        assert np.array_equal(f1[i], shifted)
+
+
+def _exchange(slabs, bufs, before):
+    """One face exchange around an odd step (see lbm_face_pack): pack every
+    slab's two faces, then unpack them into the neighbours."""
+    m = len(slabs)
+    for j, s in enumerate(slabs):
+        s.face_pack(0, bufs[j][0])
+        s.face_pack(1, bufs[j][1])
+    for j, s in enumerate(slabs):
+        if before:
+            # S_j.face0 <- S_{j+1}.face0, S_j.face1 <- S_{j-1}.face1
+            s.face_unpack(0, bufs[(j + 1) % m][0])
+            s.face_unpack(1, bufs[(j - 1) % m][1])
+        else:
+            # S_{j+1}.face0 <- S_j.face0, S_{j-1}.face1 <- S_j.face1
+            s.face_unpack(0, bufs[(j - 1) % m][0])
+            s.face_unpack(1, bufs[(j + 1) % m][1])
+
+
+@pytest.mark.parametrize("prec", [lbm.LBM_F64, lbm.LBM_F32, lbm.LBM_F16S])
+@pytest.mark.parametrize("q,heights,nx", [(19, (7, 6, 7), 21), (27, (5, 1, 6), 64), (27, (4, 4), 21)])
+def test_slabs_with_face_exchange_equal_whole_lattice(prec, q, heights, nx):
+    """Slabs of unequal heights (one a single plane) stacked along z, each its own
+    periodic lattice, exchanging faces around every odd step: every population of
+    every slab equals the whole lattice's bit for bit at even times (natural
+    layout).  Three slabs make the exchange a rotation, not a swap, so a face
+    sent the wrong way fails; nx = 64 takes the FP16 row form."""
+    import torch
+    ny = 10
+    nz = sum(heights)
+    tag = inputs.TAG_SMAG if q == 27 else inputs.TAG_BGK
+    kw = dict(q=q, prec=prec, tau=0.56, smag_cs=0.1, force=(1e-5, 0.0, -2e-6))
+    rho, u = inputs.random_fields(nx, ny, nz, seed=71, du=0.03, drho=0.01)
+    whole = lbm.Lattice(inputs.all_fluid(nx, ny, nz, tag), **kw)
+    whole.init_equilibrium(rho, u)
+    slabs, z0 = [], 0
+    for h in heights:
+        s = lbm.Lattice(inputs.all_fluid(nx, ny, h, tag), **kw)
+        s.init_equilibrium(rho[z0:z0 + h], u[:, z0:z0 + h])
+        slabs.append(s)
+        z0 += h
+    m = lbm.lbm_face_populations(q)
+    dt = {lbm.LBM_F64: torch.float64, lbm.LBM_F32: torch.float32, lbm.LBM_F16S: torch.float16}[prec]
+    bufs = [[torch.empty(m * nx * ny, dtype=dt, device="cuda") for _ in range(2)] for _ in slabs]
+    for t in range(12):
+        odd = whole.time % 2 == 1
+        if odd:
+            _exchange(slabs, bufs, before=True)
+        for s in slabs:
+            s.step(1)
+        if odd:
+            _exchange(slabs, bufs, before=False)
+        whole.step(1)
+        if whole.time % 2 == 0 and whole.time in (2, 12):
+            fw = whole.read_state()
+            parts = np.concatenate([s.read_state() for s in slabs], axis=1)
+            assert np.array_equal(parts, fw), whole.time
+    torch.cuda.synchronize()
+
+
+def test_face_populations_and_errors():
+    assert lbm.lbm_face_populations(19) == 5 and lbm.lbm_face_populations(27) == 9
+    assert lbm.lbm_face_populations(9) == 0
+    import torch
+    L = lbm.Lattice(inputs.all_fluid(8, 8, 4), q=19)
+    buf = torch.empty(5 * 64, dtype=torch.float64, device="cuda")
+    with pytest.raises(lbm.LbmError) as e:
+        L.face_pack(2, buf)
+    assert e.value.status == lbm.LBM_EINVAL
+
+
+@pytest.mark.parametrize("lane", [4, 8, 16])
+def test_bandwidth_probe_moves_the_bytes(lane):
+    import torch
+    nbytes = 4096 * lane * 16
+    src = torch.arange(nbytes // 4, dtype=torch.int32, device="cuda")
+    dst = torch.zeros_like(src)
+    lbm.lbm_probe_bandwidth(0, dst, src, nbytes, lane)
+    torch.cuda.synchronize()
+    assert torch.equal(dst, src)
+    dst.zero_()
+    lbm.lbm_probe_bandwidth(2, dst, None, nbytes, lane)
+    torch.cuda.synchronize()
+    # each lane writes its own index into every 32-bit word of its vectors
+    per = lane // 4
+    lanes = (torch.arange(nbytes // 4, device="cuda") // per) % 256
+    assert torch.equal(dst.long(), lanes)
+    dst.zero_()
+    lbm.lbm_probe_bandwidth(1, dst, src, nbytes, lane)
+    torch.cuda.synchronize()
+    assert int(dst.count_nonzero()) == 0
