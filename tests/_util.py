@@ -50,3 +50,16 @@ def momentum_bound(f_gpu, f_orc, tags, q):
     d = np.abs(f_gpu[:, m] - f_orc[:, m]).sum(axis=1)      # [q]
     s = np.abs(f_orc[:, m]).sum(axis=1)                    # [q]
     return np.abs(c).T @ d + 64 * 2.0 ** -53 * (np.abs(c).T @ s)
+
+
+def kinetic_energy_bound(u_gpu, u_orc, tags):
+    """Largest difference two sums K = sum 1/2 |u|^2 over fluid nodes can show when
+    the node velocities differ by u_gpu - u_orc: per node
+    |1/2 |a|^2 - 1/2 |b|^2| = 1/2 |(a - b) . (a + b)| <= 1/2 |a - b| |a + b|
+    (Cauchy-Schwarz), summed, plus the rounding of two sums of the same terms
+    (64 unit roundoffs of K).  K is quadratic in u, so its relative difference
+    is about twice that of the velocity field."""
+    m = fluid_mask(tags)
+    a, b = u_gpu[:, m], u_orc[:, m]
+    per_node = 0.5 * np.linalg.norm(a - b, axis=0) * np.linalg.norm(a + b, axis=0)
+    return float(per_node.sum() + 64 * 2.0 ** -53 * 0.5 * (b * b).sum())

@@ -22,7 +22,7 @@ import pytest
 import oracle
 from paper_2506_09242_amd import inputs, lbm
 
-from _util import fluid_mask, max_rel_pop_error, momentum_bound, rel_l2
+from _util import fluid_mask, kinetic_energy_bound, max_rel_pop_error, momentum_bound, rel_l2
 
 pytestmark = pytest.mark.gpu
 
@@ -108,7 +108,13 @@ def test_config64_fp64_matches_oracle(name):
     nf = m["n_fluid"]
     assert nf == m_o["n_fluid"]
     assert abs(m["mass_delta"] - m_o["mass_delta"]) <= TOL * nf
-    assert abs(m["kinetic_energy"] * nf / m_o["ke_sum"] - 1.0) <= TOL
+    # kinetic energy: quadratic in u, so bounded by the velocities' own
+    # differences rather than by 1e-12 (with slow flow through the porous medium
+    # its relative difference is about twice that of u)
+    dk = abs(m["kinetic_energy"] * nf - m_o["ke_sum"])
+    k_bound = kinetic_energy_bound(u_g, u_o, tags)
+    print(name, "kinetic energy diff", dk, "bound", k_bound, "relative", dk / m_o["ke_sum"], flush=True)
+    assert dk <= k_bound and dk <= 4 * TOL * m_o["ke_sum"]
     # momentum: no larger than the populations' own differences allow (the sum
     # cancels heavily, so its relative error exceeds theirs)
     bound = momentum_bound(f, f_o, tags, _config(name)[1]["q"])
@@ -120,12 +126,16 @@ def test_config64_fp64_matches_oracle(name):
 # lattice) against the FP64 oracle after the configuration's steps: FP32
 # arithmetic and storage round at 2^-24 per operation, FP16 storage rounds the
 # stored h = f - w rho0 at 2^-11 once per step; both errors accumulate over
-# the steps of a laminar run.  Bounds are about ten times the errors measured
-# on MI355X (printed by the test) and far below the velocity scale itself.
+# the steps of a laminar run.  Bounds are five to ten times the errors
+# measured on MI355X (printed by the test; velocity rel. L2 / k rel. error):
+#   cavity  FP32 1.9e-5 / 2.4e-5   FP16 4.5e-4 / 3.7e-5
+#   porous  FP32 3.9e-6 / 9.1e-7   FP16 4.8e-3 / 2.3e-3
+#   TGV     FP32 1.0e-5 / 1.9e-5   FP16 1.0e-3 / 8.7e-5
+# and far below the velocity scale itself.
 REDUCED_BOUNDS = {
-    ("cavity", lbm.LBM_F32): 1e-5, ("cavity", lbm.LBM_F16S): 2e-2,
-    ("porous", lbm.LBM_F32): 1e-4, ("porous", lbm.LBM_F16S): 1e-1,
-    ("tgv", lbm.LBM_F32): 1e-5, ("tgv", lbm.LBM_F16S): 2e-2,
+    ("cavity", lbm.LBM_F32): 1e-4, ("cavity", lbm.LBM_F16S): 3e-3,
+    ("porous", lbm.LBM_F32): 3e-5, ("porous", lbm.LBM_F16S): 3e-2,
+    ("tgv", lbm.LBM_F32): 1e-4, ("tgv", lbm.LBM_F16S): 6e-3,
 }
 
 
