@@ -220,6 +220,26 @@ lbm_status lbm_step(lbm_lattice *lat, int64_t n_steps);
 lbm_status lbm_step_reduce(lbm_lattice *lat, int64_t n_steps, int64_t every, lbm_moments *series,
                            int64_t n_series);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * steps, reductions and results as lbm_step_reduce (bitwise, same kernels),
+ * with the reduction scratch -- per-tile partials, the finalize stage and the
+ * sample series -- in one fixed array per GPU that the library holds until the
+ * process ends (NRED = 10 doubles per tile, per finalize block and per sample:
+ * about 48 MB).  Makes no hipMalloc, hipFree or other allocating call; the
+ * first call on a device resolves that array's address there.  Limits:
+ * n_steps/every + 1 <= LBM_NOALLOC_MAX_SAMPLES samples and at most
+ * LBM_NOALLOC_MAX_TILES tiles of 256 nodes in the lattice's current tiling
+ * (any lattice up to about 1.5e8 nodes, e.g. 512^3); EINVAL beyond either,
+ * with the numbers in lbm_last_error().  Every call on one GPU shares that
+ * GPU's array (nothing in it needs clearing: each call writes what it
+ * reads), so calls that overlap in time on one GPU -- from two threads, or on
+ * two streams -- race and must be serialised by the caller.  Synchronizes. */
+#define LBM_NOALLOC_MAX_TILES 589824
+#define LBM_NOALLOC_MAX_SAMPLES 4096
+lbm_status lbm_step_reduce_noalloc(lbm_lattice *lat, int64_t n_steps, int64_t every, lbm_moments *series,
+                                   int64_t n_series);
+
 /* Reductions of the current state (a standalone pass): the domain sums of
  * Sec. 2.2 ("Reductions", the transform_reduce of every node's moments) with
  * the kinetic energy of Eq. (5); fields as in lbm_moments, FP64 per node,

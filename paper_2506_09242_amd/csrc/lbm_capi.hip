@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -60,6 +61,7 @@ struct lbm_lattice {
     int tiles_x = 1, tiles_y = 1, n_tiles = 1;
     long long n_fluid = 0;
     bool failed = false;
+    int device = 0;                 // HIP device current at create
     char variant[96] = {0};
 };
 
@@ -490,7 +492,8 @@ static lbm_status create_impl(const lbm_config *cfg, const uint8_t *tags_host, v
         lbm_destroy(L);
         return st;
     };
-    hipError_t e;
+    hipError_t e = hipGetDevice(&L->device);
+    if (e != hipSuccess) return bail(set_err(LBM_EHIP, "hipGetDevice: %s", hipGetErrorString(e)));
     if (pops_dev) {
         L->d_pops = pops_dev;
         L->own_pops = false;
@@ -672,9 +675,15 @@ extern "C" lbm_status lbm_init_equilibrium(lbm_lattice *lat, const double *rho_h
 }
 
 // --------------------------------------------------------------- stepping
-static lbm_status launch_one(lbm_lattice *lat, int mode) {
+// partials: where MODE_STEP_REDUCE / MODE_REDUCE write the per-tile sums
+// ([NRED][stride]); null = the lattice's own buffer.
+static lbm_status launch_one(lbm_lattice *lat, int mode, double *partials = nullptr, long long stride = 0) {
     const Launchers Lc = pick(lat->cfg.q, lat->cfg.prec);
-    const StepParams p = step_params(lat);
+    StepParams p = step_params(lat);
+    if (partials) {
+        p.partials = partials;
+        p.partial_stride = stride;
+    }
     HIPCHK(lat, Lc.step(p, lat->ms, lat->tagged, mode, lat->parity, lat->stream));
     if (mode != MODE_REDUCE) {
         lat->parity ^= 1;
@@ -719,6 +728,48 @@ static void fill_moments(const lbm_lattice *lat, const double *v, int64_t step, 
     m->kinetic_energy_rho = v[8];
 }
 
+// Shared by lbm_step_reduce and lbm_step_reduce_noalloc: the step loop with
+// fused reductions every `every` steps into partials ([NRED][stride]), the
+// two-stage finalize through stage1 into d_series ([ns][NRED]), and the copy
+// of the samples to the host through a fixed stack buffer.
+static lbm_status step_reduce_impl(lbm_lattice *lat, int64_t n_steps, int64_t every, lbm_moments *series,
+                                   double *partials, long long stride, double *stage1, double *d_series) {
+    const int64_t ns = n_steps / every + 1;
+    const int64_t t0 = lat->t;
+    lbm_status st;
+    for (int64_t s = 0; s < n_steps; ++s) {
+        if (s % every == 0) {
+            st = launch_one(lat, MODE_STEP_REDUCE, partials, stride);
+            if (st != LBM_OK) return st;
+            HIPCHK(lat, launch_finalize(partials, stride, lat->n_tiles, stage1, d_series + (s / every) * NRED,
+                                        lat->stream));
+        } else {
+            st = launch_one(lat, MODE_STEP);
+            if (st != LBM_OK) return st;
+        }
+    }
+    if (n_steps % every == 0) {
+        st = launch_one(lat, MODE_REDUCE, partials, stride);
+        if (st != LBM_OK) return st;
+        HIPCHK(lat, launch_finalize(partials, stride, lat->n_tiles, stage1, d_series + (ns - 1) * NRED, lat->stream));
+    }
+    constexpr int64_t kBatch = 64;
+    double h[kBatch * NRED];
+    bool bad = false;
+    for (int64_t k0 = 0; k0 < ns; k0 += kBatch) {
+        const int64_t cnt = std::min(kBatch, ns - k0);
+        HIPCHK(lat, hipMemcpyAsync(h, d_series + k0 * NRED, (size_t)cnt * NRED * sizeof(double),
+                                   hipMemcpyDeviceToHost, lat->stream));
+        HIPCHK(lat, hipStreamSynchronize(lat->stream));
+        for (int64_t k = 0; k < cnt; ++k) {
+            fill_moments(lat, h + k * NRED, t0 + (k0 + k) * every, &series[k0 + k]);
+            if (series[k0 + k].n_nonfinite > 0) bad = true;
+        }
+    }
+    if (bad) return set_err(LBM_EUNSTABLE, "non-finite density or velocity found");
+    return LBM_OK;
+}
+
 extern "C" lbm_status lbm_step_reduce(lbm_lattice *lat, int64_t n_steps, int64_t every, lbm_moments *series,
                                       int64_t n_series) {
     CHECK_HANDLE(lat);
@@ -727,35 +778,64 @@ extern "C" lbm_status lbm_step_reduce(lbm_lattice *lat, int64_t n_steps, int64_t
     if (!series || n_series < ns) return set_err(LBM_EINVAL, "series needs %lld entries", (long long)ns);
     lbm_status st = ensure_series(lat, ns);
     if (st != LBM_OK) return st;
-    const int64_t t0 = lat->t;
-    for (int64_t s = 0; s < n_steps; ++s) {
-        if (s % every == 0) {
-            st = launch_one(lat, MODE_STEP_REDUCE);
-            if (st != LBM_OK) return st;
-            HIPCHK(lat, launch_finalize(lat->d_partials, lat->max_tiles, lat->n_tiles, lat->d_stage1,
-                                        lat->d_series + (s / every) * NRED, lat->stream));
-        } else {
-            st = launch_one(lat, MODE_STEP);
-            if (st != LBM_OK) return st;
-        }
+    return step_reduce_impl(lat, n_steps, every, series, lat->d_partials, lat->max_tiles, lat->d_stage1,
+                            lat->d_series);
+}
+
+// ------------------------------------------- allocation-free step + reduce
+// The reduction scratch of lbm_step_reduce_noalloc: per-tile partials, the
+// finalize stage and the sample series, in one array per GPU that lives as
+// long as the process.  In host code `scratch` only names the symbol; its
+// device address comes from hipGetSymbolAddress, once per device.
+namespace {
+constexpr long long kNoAllocTiles = LBM_NOALLOC_MAX_TILES;
+constexpr long long kNoAllocSamples = LBM_NOALLOC_MAX_SAMPLES;
+constexpr long long kScratchDoubles = NRED * kNoAllocTiles + NRED * kFinalizeBlocks + NRED * kNoAllocSamples;
+__device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `dev` (resolved with dev current, then cached).
+lbm_status scratch_on(int dev, double **out) {
+    if (dev < 0 || dev >= kMaxDevices) return set_err(LBM_EUNSUPPORTED, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e == hipSuccess && cur != dev) e = hipSetDevice(dev);
+        void *ptr = nullptr;
+        if (e == hipSuccess) e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (cur >= 0 && cur != dev) (void)hipSetDevice(cur);
+        if (e != hipSuccess || !ptr)
+            return set_err(LBM_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<double *>(ptr);
     }
-    if (n_steps % every == 0) {
-        st = launch_one(lat, MODE_REDUCE);
-        if (st != LBM_OK) return st;
-        HIPCHK(lat, launch_finalize(lat->d_partials, lat->max_tiles, lat->n_tiles, lat->d_stage1,
-                                    lat->d_series + (ns - 1) * NRED, lat->stream));
-    }
-    std::vector<double> h((size_t)ns * NRED);
-    HIPCHK(lat, hipMemcpyAsync(h.data(), lat->d_series, h.size() * sizeof(double), hipMemcpyDeviceToHost,
-                               lat->stream));
-    HIPCHK(lat, hipStreamSynchronize(lat->stream));
-    bool bad = false;
-    for (int64_t k = 0; k < ns; ++k) {
-        fill_moments(lat, h.data() + k * NRED, t0 + k * every, &series[k]);
-        if (series[k].n_nonfinite > 0) bad = true;
-    }
-    if (bad) return set_err(LBM_EUNSTABLE, "non-finite density or velocity found");
+    *out = g_scratch_ptr[dev];
     return LBM_OK;
+}
+}  // namespace
+
+extern "C" lbm_status lbm_step_reduce_noalloc(lbm_lattice *lat, int64_t n_steps, int64_t every,
+                                              lbm_moments *series, int64_t n_series) {
+    CHECK_HANDLE(lat);
+    if (n_steps < 0 || every < 1) return set_err(LBM_EINVAL, "need n_steps >= 0 and every >= 1");
+    const int64_t ns = n_steps / every + 1;
+    if (!series || n_series < ns) return set_err(LBM_EINVAL, "series needs %lld entries", (long long)ns);
+    if (ns > kNoAllocSamples)
+        return set_err(LBM_EINVAL, "%lld samples exceed the allocation-free limit of %lld", (long long)ns,
+                       kNoAllocSamples);
+    if (lat->n_tiles > kNoAllocTiles)
+        return set_err(LBM_EINVAL, "%d tiles exceed the allocation-free limit of %lld (about %lld nodes)",
+                       lat->n_tiles, kNoAllocTiles, kNoAllocTiles * 256);
+    double *base = nullptr;
+    lbm_status st = scratch_on(lat->device, &base);
+    if (st != LBM_OK) return st;
+    double *partials = base;
+    double *stage1 = base + NRED * kNoAllocTiles;
+    double *d_series = stage1 + NRED * kFinalizeBlocks;
+    return step_reduce_impl(lat, n_steps, every, series, partials, kNoAllocTiles, stage1, d_series);
 }
 
 extern "C" lbm_status lbm_reduce(lbm_lattice *lat, lbm_moments *out) {

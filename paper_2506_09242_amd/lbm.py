@@ -62,6 +62,7 @@ SIGNATURES = {
     "lbm_init_equilibrium": (C.c_int, [_P, _P, _P]),
     "lbm_step": (C.c_int, [_P, C.c_int64]),
     "lbm_step_reduce": (C.c_int, [_P, C.c_int64, C.c_int64, C.POINTER(LbmMoments), C.c_int64]),
+    "lbm_step_reduce_noalloc": (C.c_int, [_P, C.c_int64, C.c_int64, C.POINTER(LbmMoments), C.c_int64]),
     "lbm_reduce": (C.c_int, [_P, C.POINTER(LbmMoments)]),
     "lbm_synchronize": (C.c_int, [_P]),
     "lbm_enstrophy": (C.c_int, [_P, C.POINTER(C.c_double)]),
@@ -278,10 +279,12 @@ class Lattice:
     def step(self, n):
         _check(lib().lbm_step(self.h, int(n)))
 
-    def step_reduce(self, n, every):
+    def step_reduce(self, n, every, noalloc=False):
+        """lbm_step_reduce, or lbm_step_reduce_noalloc (noalloc=True)."""
         ns = int(n) // int(every) + 1
         arr = (LbmMoments * ns)()
-        rc = lib().lbm_step_reduce(self.h, int(n), int(every), arr, ns)
+        fn = lib().lbm_step_reduce_noalloc if noalloc else lib().lbm_step_reduce
+        rc = fn(self.h, int(n), int(every), arr, ns)
         series = [m.as_dict() for m in arr]
         if rc == LBM_EUNSTABLE:
             raise LbmError(rc, lbm_last_error())

@@ -129,6 +129,7 @@ def test_null_handles_are_rejected():
     L = lbm.lib()
     assert L.lbm_step(None, 1) == lbm.LBM_EINVAL
     assert L.lbm_set_launch(None, 64, 4) == lbm.LBM_EINVAL
+    assert L.lbm_step_reduce_noalloc(None, 1, 1, None, 0) == lbm.LBM_EINVAL
     L.lbm_destroy(None)  # no-op
     assert L.lbm_time(None) == -1
 
