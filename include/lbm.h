@@ -315,7 +315,8 @@ lbm_status lbm_write_state(lbm_lattice *lat, const double *h_host, int64_t t);
  * LBM_MLP_NPARAMS floats, packed W1[32][7], b1[32], W2[32][32], b2[32],
  * W3[32], b3, mean[7], std[7].  Weights are rounded to BF16 on upload; biases
  * and normalisation stay FP32.  Inputs: the non-equilibrium momentum flux
- * Pi_xx, Pi_yy, Pi_zz, Pi_xy, Pi_xz, Pi_yz and rho, z-scored.  Output:
+ * Pi_xx, Pi_yy, Pi_zz, Pi_xy, Pi_xz, Pi_yz and rho, z-scored in FP32
+ * ((x - mean) times the FP32 reciprocal of std).  Output:
  * nu_t = nu0 * softplus(W3 h2 + b3), nu0 = (tau - 1/2)/3; tau_eff =
  * 3 (nu0 + nu_t) + 1/2.  Non-finite nu_t or nu_t > 10 nu0 falls back to the
  * Smagorinsky tau_eff.  Until called, MLP nodes use the Smagorinsky value. */

@@ -229,8 +229,9 @@ void orc_equilibrium(int q, double rho, const double u[3], double *feq) {
  * Packed parameter vector (floats): W1[32][7], b1[32], W2[32][32], b2[32],
  * W3[32], b3, mean[7], std[7]  (1359 values).  Inputs are the six
  * non-equilibrium stress moments (xx,yy,zz,xy,xz,yz) and rho, z-scored with
- * mean/std.  Hidden layers use ReLU; the output passes through softplus and
- * is scaled by the molecular viscosity nu0, giving the eddy viscosity.
+ * mean/std in FP32 (x - mean times the FP32 reciprocal of std).  Hidden
+ * layers use ReLU; the output passes through softplus and is scaled by the
+ * molecular viscosity nu0, giving the eddy viscosity.
  * Inputs, weights and hidden activations are rounded to bfloat16 (round to
  * nearest, ties to even) before each product, as the device does; sums are
  * FP64 here.  Biases stay FP32.
@@ -254,7 +255,8 @@ static double mlp_eddy_viscosity(const float *P, const double feat[7], double nu
     const float *W1 = P, *b1 = P + 224, *W2 = P + 256, *b2 = P + 1280, *W3 = P + 1312;
     const float *b3 = P + 1344, *mean = P + 1345, *sd = P + 1352;
     double x[7], h1[32], h2[32];
-    for (int k = 0; k < 7; ++k) x[k] = bf16_round(((float)feat[k] - mean[k]) / sd[k]);
+    /* z-score in FP32: (x - mean) times the FP32 reciprocal of std */
+    for (int k = 0; k < 7; ++k) x[k] = bf16_round(((float)feat[k] - mean[k]) * (1.0f / sd[k]));
     for (int o = 0; o < 32; ++o) {
         double s = 0.0;
         for (int k = 0; k < 7; ++k) s += bf16_round(W1[o * 7 + k]) * x[k];

@@ -49,14 +49,14 @@ constexpr int NRED = 10;
 // patterns) followed by FP32 biases and normalisation (see lbm_mlp.hip).
 struct MlpDev {
     const uint16_t *w1;   // [32][8]: W1 rows padded from 7 to 8 inputs (zero)
-    const uint16_t *w2;   // [2 m-tiles][4 lane groups][16 rows][8 slots], columns
+    const uint16_t *w2;   // [2 products][2 lane groups][32 rows][8 K slots], columns
                           // permuted to the layer-1 accumulator order
-    const float *b1;      // [32]
-    const float *b2;      // [32]
-    const float *w3;      // [32] FP32 copy of the BF16-rounded W3
+    const uint16_t *w3;   // [2 lane groups][16]: W3 in accumulator order
+    const float *b1;      // [2 lane groups][16]: b1 in accumulator order
+    const float *b2;      // [2 lane groups][16]: b2 in accumulator order
     const float *b3;      // [1]
     const float *mean;    // [7]
-    const float *sd;      // [7] standard deviations
+    const float *inv_sd;  // [7] FP32 reciprocals of the standard deviations
 };
 
 struct StepParams {

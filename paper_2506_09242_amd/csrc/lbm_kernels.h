@@ -298,6 +298,87 @@ __device__ __forceinline__ void collide_regularized(const C (&h)[Q], int tag, co
     });
 }
 
+// BGK with a per-node relaxation time from the eddy-viscosity closure (tag
+// BGK+MLP), from Smagorinsky (tag BGK+Smagorinsky, and the closure's
+// fallback) or the plain one (tag BGK), for lattices whose fluid nodes use
+// only these three models.  The non-equilibrium momentum flux comes from the
+// second moment of h minus that of the second-order equilibrium (dRho/3 I +
+// rho u u, exact on D3Q19 and D3Q27), and the network is evaluated before the
+// equilibrium is formed, pair by pair where it is used: only the populations
+// and a few moments are live across the matrix-core products.
+template <int Q, typename C, int MS>
+__device__ __forceinline__ void collide_closure(const C (&h)[Q], int tag, bool live, const StepParams &p,
+                                                C (&hs)[Q]) {
+    constexpr int H = (Q - 1) / 2;
+    C drho = C(0), jx = C(0), jy = C(0), jz = C(0);
+    C sxx = C(0), syy = C(0), szz = C(0), sxy = C(0), sxz = C(0), syz = C(0);
+    sfor<Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        using Vi = V<Q, i>;
+        drho += h[i];
+        if constexpr (Vi::x == 1) jx += h[i];
+        if constexpr (Vi::x == -1) jx -= h[i];
+        if constexpr (Vi::y == 1) jy += h[i];
+        if constexpr (Vi::y == -1) jy -= h[i];
+        if constexpr (Vi::z == 1) jz += h[i];
+        if constexpr (Vi::z == -1) jz -= h[i];
+        if constexpr (Vi::x != 0) sxx += h[i];
+        if constexpr (Vi::y != 0) syy += h[i];
+        if constexpr (Vi::z != 0) szz += h[i];
+        if constexpr (Vi::x * Vi::y == 1) sxy += h[i];
+        if constexpr (Vi::x * Vi::y == -1) sxy -= h[i];
+        if constexpr (Vi::x * Vi::z == 1) sxz += h[i];
+        if constexpr (Vi::x * Vi::z == -1) sxz -= h[i];
+        if constexpr (Vi::y * Vi::z == 1) syz += h[i];
+        if constexpr (Vi::y * Vi::z == -1) syz -= h[i];
+    });
+    const C Fx = (C)p.force[0], Fy = (C)p.force[1], Fz = (C)p.force[2];
+    const C rho = (C)p.rho0 + drho;
+    const C inv_rho = C(1) / rho;
+    const C ux = (jx + C(0.5) * Fx) * inv_rho;
+    const C uy = (jy + C(0.5) * Fy) * inv_rho;
+    const C uz = (jz + C(0.5) * Fz) * inv_rho;
+    const C d3 = drho * C(1.0 / 3.0);
+    const C pxx = sxx - d3 - rho * ux * ux, pyy = syy - d3 - rho * uy * uy, pzz = szz - d3 - rho * uz * uz;
+    const C pxy = sxy - rho * ux * uy, pxz = sxz - rho * ux * uz, pyz = syz - rho * uy * uz;
+
+    const C qn = sqrt(pxx * pxx + pyy * pyy + pzz * pzz + C(2) * (pxy * pxy + pxz * pxz + pyz * pyz));
+    const C tau0 = (C)p.tau;
+    C tau_eff = C(0.5) * (tau0 + sqrt(tau0 * tau0 + (C)p.smag_c * qn * inv_rho));
+    const bool want = live && tag == LBM_TAG_BGK_MLP;
+    if (p.has_mlp && __any(want)) {
+        const float feat[7] = {(float)pxx, (float)pyy, (float)pzz, (float)pxy, (float)pxz, (float)pyz, (float)rho};
+        const float sp = mlp_wave_eval(p.mlp, feat);
+        const C nu0 = (C)p.nu0;
+        const C nut = nu0 * (C)sp;
+        if (want && isfinite(nut) && nut <= C(10) * nu0) tau_eff = C(3) * (nu0 + nut) + C(0.5);
+    }
+    const C w = (tag == LBM_TAG_BGK_SMAG || tag == LBM_TAG_BGK_MLP) ? C(1) / tau_eff : (C)p.omega;
+
+    const C uu = ux * ux + uy * uy + uz * uz;
+    const C uF = ux * Fx + uy * Fy + uz * Fz;
+    const C g = C(1) - C(0.5) * w;
+    hs[0] = h[0] - w * (h[0] - C(V<Q, 0>::w) * (drho - C(1.5) * rho * uu)) + g * C(V<Q, 0>::w) * C(-3) * uF;
+    sfor<H>([&](auto K) {
+        constexpr int k = decltype(K)::value + 1;
+        using Vk = V<Q, k>;
+        C cu = C(0), cF = C(0);
+        if constexpr (Vk::x != 0) cu += C(Vk::x) * ux, cF += C(Vk::x) * Fx;
+        if constexpr (Vk::y != 0) cu += C(Vk::y) * uy, cF += C(Vk::y) * Fy;
+        if constexpr (Vk::z != 0) cu += C(Vk::z) * uz, cF += C(Vk::z) * Fz;
+        const C ev = C(Vk::w) * (drho + rho * (C(4.5) * cu * cu - C(1.5) * uu));
+        const C od = C(Vk::w) * C(3) * rho * cu;
+        const C Fe = C(Vk::w) * (C(9) * cu * cF - C(3) * uF);
+        const C Fo = C(Vk::w) * C(3) * cF;
+        const C hp = C(0.5) * (h[k] + h[k + H]);
+        const C hm = C(0.5) * (h[k] - h[k + H]);
+        const C A = g * Fe - w * (hp - ev);
+        const C B = g * Fo - w * (hm - od);
+        hs[k] = h[k] + A + B;
+        hs[k + H] = h[k + H] + A - B;
+    });
+}
+
 // MOM: regularized / recursive-regularized lattices take the moment-only
 // update (collide_regularized); the caller decides where that pays.
 template <int Q, typename C, int MS, bool MOM = false>
@@ -309,6 +390,10 @@ __device__ __forceinline__ void collide_node(const C (&h)[Q], int tag, bool live
     }
     if constexpr (MOM && (MS == MS_REG || MS == MS_RR)) {
         collide_regularized<Q, C, MS>(h, tag, p, hs);
+        return;
+    }
+    if constexpr (MS == (MS_BGK | MS_SMAG | MS_MLP)) {
+        collide_closure<Q, C, MS>(h, tag, live, p, hs);
         return;
     }
     constexpr int H = (Q - 1) / 2;

@@ -46,55 +46,57 @@ uint16_t bf16_bits(float v) {
     b += 0x7fffu + ((b >> 16) & 1u);
     return (uint16_t)(b >> 16);
 }
-float bf16_value(uint16_t h) {
-    uint32_t b = (uint32_t)h << 16;
-    float v;
-    std::memcpy(&v, &b, 4);
-    return v;
-}
 
-// Device block: w1p[256] u16 | w2p[1024] u16 | b1[32] b2[32] w3[32] b3[1] pad[3] mean[7] pad sd[7] pad
-constexpr size_t kBlockBytes = (256 + 1024) * 2 + (32 + 32 + 32 + 4 + 8 + 8) * 4;
+// Device block (see MlpDev): w1p[32][8] u16 | w2p[2][2][32][8] u16 | w3p[2][16] u16 |
+// b1p[2][16] b2p[2][16] b3[1] pad[3] mean[7] pad inv_sd[7] pad (floats).  "Accumulator
+// order" of lane group g: entry r is neuron 8 (r / 4) + 4 g + r % 4 (lbm_mlp_device.h).
+constexpr size_t kW3Off = (256 + 1024) * 2, kFloatOff = kW3Off + 32 * 2;
+constexpr size_t kBlockBytes = kFloatOff + (32 + 32 + 4 + 8 + 8) * 4;
+
+int acc_neuron(int r, int g) { return 8 * (r / 4) + 4 * g + (r % 4); }
 
 void pack_block(const float *P, std::vector<unsigned char> &out) {
     out.assign(kBlockBytes, 0);
     uint16_t *w1p = reinterpret_cast<uint16_t *>(out.data());
     uint16_t *w2p = w1p + 256;
-    float *fl = reinterpret_cast<float *>(w2p + 1024);
+    uint16_t *w3p = reinterpret_cast<uint16_t *>(out.data() + kW3Off);
+    float *fl = reinterpret_cast<float *>(out.data() + kFloatOff);
     for (int o = 0; o < 32; ++o)
         for (int s = 0; s < 8; ++s) w1p[o * 8 + s] = s < 7 ? bf16_bits(P[OW1 + o * 7 + s]) : 0;
-    for (int mt = 0; mt < 2; ++mt)
-        for (int g = 0; g < 4; ++g)
-            for (int m = 0; m < 16; ++m)
-                for (int s = 0; s < 8; ++s) {
-                    const int col = s < 4 ? 4 * g + s : 16 + 4 * g + (s - 4);
-                    w2p[((mt * 4 + g) * 16 + m) * 8 + s] = bf16_bits(P[OW2 + (16 * mt + m) * 32 + col]);
-                }
-    for (int k = 0; k < 32; ++k) {
-        fl[k] = P[OB1 + k];
-        fl[32 + k] = P[OB2 + k];
-        fl[64 + k] = bf16_value(bf16_bits(P[OW3 + k]));
-    }
-    fl[96] = P[OB3];
+    // W2 as the A operands of the two layer-2 products: product p, lane group g,
+    // row i, K slot s holds W2[i][neuron], the neuron that accumulator register
+    // 8p + s of lane group g holds after layer 1
+    for (int pr = 0; pr < 2; ++pr)
+        for (int g = 0; g < 2; ++g)
+            for (int i = 0; i < 32; ++i)
+                for (int s = 0; s < 8; ++s)
+                    w2p[((pr * 2 + g) * 32 + i) * 8 + s] = bf16_bits(P[OW2 + i * 32 + acc_neuron(8 * pr + s, g)]);
+    for (int g = 0; g < 2; ++g)
+        for (int r = 0; r < 16; ++r) {
+            const int o = acc_neuron(r, g);
+            w3p[g * 16 + r] = bf16_bits(P[OW3 + o]);
+            fl[g * 16 + r] = P[OB1 + o];
+            fl[32 + g * 16 + r] = P[OB2 + o];
+        }
+    fl[64] = P[OB3];
     for (int k = 0; k < 7; ++k) {
-        fl[100 + k] = P[OMEAN + k];
-        fl[108 + k] = P[OSTD + k];
+        fl[68 + k] = P[OMEAN + k];
+        fl[76 + k] = 1.0f / P[OSTD + k];
     }
 }
 
 MlpDev block_view(void *d) {
     MlpDev m;
-    uint16_t *w1p = static_cast<uint16_t *>(d);
-    uint16_t *w2p = w1p + 256;
-    float *fl = reinterpret_cast<float *>(w2p + 1024);
-    m.w1 = w1p;
-    m.w2 = w2p;
+    unsigned char *b = static_cast<unsigned char *>(d);
+    float *fl = reinterpret_cast<float *>(b + kFloatOff);
+    m.w1 = reinterpret_cast<uint16_t *>(b);
+    m.w2 = m.w1 + 256;
+    m.w3 = reinterpret_cast<uint16_t *>(b + kW3Off);
     m.b1 = fl;
     m.b2 = fl + 32;
-    m.w3 = fl + 64;
-    m.b3 = fl + 96;
-    m.mean = fl + 100;
-    m.sd = fl + 108;
+    m.b3 = fl + 64;
+    m.mean = fl + 68;
+    m.inv_sd = fl + 76;
     return m;
 }
 

@@ -1,21 +1,27 @@
 // lbm_mlp_device.h -- wavefront-wide evaluation of the eddy-viscosity closure
 // network (7 -> 32 -> 32 -> 1, ReLU, softplus) on BF16 matrix cores.
 //
-// One wavefront evaluates its 64 nodes at once with 16 v_mfma_f32_16x16x32_bf16
-// (8 per hidden layer).  Neurons are the M dimension, nodes the N dimension
-// (four 16-node tiles per wave).  No lane exchange is needed:
-//  - layer 1: for node tile t only lane group t (lanes 16t..16t+15) feeds
-//    non-zero operands -- its own node's 7 features and the matching W1 rows
-//    -- so the other lane groups' K slots are zero on both sides;
-//  - layer 2: the layer-1 accumulator of lane (g, j) holds neurons
-//    4g..4g+3 and 16+4g..16+4g+3 of node j of the tile; those eight values
-//    are used directly as that lane's K slots, and W2 is stored with its
-//    columns permuted the same way (host side, lbm_mlp.hip);
-//  - layer 3 (32 -> 1) is a dot product per lane plus two xor-shuffles.
-// Only the (row = lane % 16) operand and (col = lane % 16, rows 4*(lane/16)
-// + r) accumulator layouts of the 16x16 MFMA matter; the K-slot order of the
-// operands cancels because A and B use the same per-lane slots.
-//
+// One wavefront evaluates its 64 nodes with six v_mfma_f32_32x32x16_bf16:
+// neurons are the M dimension, nodes the N dimension, one half-wave of 32
+// nodes per product (lane l's node is node l of the wave, half h = l / 32).
+// Only these layouts of the 32x32x16 product are relied on: lane l supplies
+// row (l % 32) of A and column (l % 32) of B, eight K slots each (lanes l and
+// l + 32 the two halves of K), and its accumulator register r holds output
+// row 8 (r / 4) + 4 (l / 32) + r % 4 of column l % 32 (the "accumulator
+// order" of lane group l / 32).  The order of the K slots cancels because A
+// and B use the same per-lane slots.
+//  - layer 1 (K = 7, padded to 8): for half h only the lanes of half h feed
+//    non-zero operands -- their own node's features and row l % 32 of W1 --
+//    so one product per half (two in all); the accumulator starts from b1;
+//  - layer 2 (K = 32): the layer-1 accumulator of lane l holds 16 of the 32
+//    neurons of its column's node; registers 0..7 and 8..15 are the K slots
+//    of two chained products (accumulator from b2), with W2's columns
+//    permuted to that order on the host (two per half);
+//  - layer 3 (32 -> 1): eight two-term BF16 dot products per lane over its 16
+//    neurons (W3 stored in accumulator order), plus one xor-shuffle with the
+//    partner lane l ^ 32, which holds the other 16.
+// ReLU acts on the BF16-rounded activations (rounding keeps the sign, so this
+// equals rounding the rectified value): a packed 16-bit signed max with 0.
 // Inputs, weights and hidden activations are BF16 (round to nearest even);
 // accumulation, biases and normalisation are FP32.
 #pragma once
@@ -26,8 +32,11 @@
 
 namespace lbmd {
 
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 __device__ __forceinline__ bf16x8 load_bf16x8(const uint16_t *p) {
     const uint4 v = *reinterpret_cast<const uint4 *>(p);
@@ -36,61 +45,78 @@ __device__ __forceinline__ bf16x8 load_bf16x8(const uint16_t *p) {
 
 __device__ __forceinline__ float softplus_f(float z) { return z > 20.0f ? z : log1pf(expf(z)); }
 
+// max(RNE_bf16(a), 0), max(RNE_bf16(b), 0): a negative BF16 pattern is a
+// negative 16-bit integer, so a signed max with 0 is the ReLU.
+__device__ __forceinline__ bf16x2 relu_bf16x2(float a, float b) {
+    const f32x2 f = {a, b};
+    const bf16x2 v = __builtin_convertvector(f, bf16x2);  // one paired RNE conversion
+    const s16x2 z = {0, 0};
+    return __builtin_bit_cast(bf16x2, __builtin_elementwise_max(__builtin_bit_cast(s16x2, v), z));
+}
+
+// Eight accumulator registers starting at r0 -> eight BF16 K slots.
+template <int R0>
+__device__ __forceinline__ bf16x8 relu_slots(const f32x16 &acc) {
+    bf16x8 k;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const bf16x2 v = relu_bf16x2(acc[R0 + 2 * q], acc[R0 + 2 * q + 1]);
+        k[2 * q] = v[0];
+        k[2 * q + 1] = v[1];
+    }
+    return k;
+}
+
+// 16 floats of this lane group's accumulator-order vector (biases).
+__device__ __forceinline__ f32x16 load_acc_order(const float *p) {
+    f32x16 v;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const float4 t = reinterpret_cast<const float4 *>(p)[q];
+        v[4 * q] = t.x;
+        v[4 * q + 1] = t.y;
+        v[4 * q + 2] = t.z;
+        v[4 * q + 3] = t.w;
+    }
+    return v;
+}
+
 // Returns softplus(net(x)) for this lane's node (every lane of the wave must
 // call it; lanes whose result is unused may pass any finite features).
 __device__ __forceinline__ float mlp_wave_eval(const MlpDev &m, const float feat[7]) {
     const int lane = threadIdx.x & 63;
-    const int g = lane >> 4, j = lane & 15;
+    const int g = lane >> 5, j = lane & 31;
 
     bf16x8 xo;
 #pragma unroll
-    for (int k = 0; k < 7; ++k) xo[k] = (__bf16)((feat[k] - m.mean[k]) / m.sd[k]);
+    for (int k = 0; k < 7; ++k) xo[k] = (__bf16)((feat[k] - m.mean[k]) * m.inv_sd[k]);
     xo[7] = (__bf16)0.0f;
     const bf16x8 zero = {};
-
-    const bf16x8 w1a0 = load_bf16x8(m.w1 + (0 * 16 + j) * 8);
-    const bf16x8 w1a1 = load_bf16x8(m.w1 + (1 * 16 + j) * 8);
-    const bf16x8 w2a0 = load_bf16x8(m.w2 + ((0 * 4 + g) * 16 + j) * 8);
-    const bf16x8 w2a1 = load_bf16x8(m.w2 + ((1 * 4 + g) * 16 + j) * 8);
-    const float4 b1a = *reinterpret_cast<const float4 *>(m.b1 + 4 * g);
-    const float4 b1b = *reinterpret_cast<const float4 *>(m.b1 + 16 + 4 * g);
-    const float4 b2a = *reinterpret_cast<const float4 *>(m.b2 + 4 * g);
-    const float4 b2b = *reinterpret_cast<const float4 *>(m.b2 + 16 + 4 * g);
-    const float4 w3a = *reinterpret_cast<const float4 *>(m.w3 + 4 * g);
-    const float4 w3b = *reinterpret_cast<const float4 *>(m.w3 + 16 + 4 * g);
-    const float b3 = m.b3[0];
+    const bf16x8 w1 = load_bf16x8(m.w1 + j * 8);
+    const f32x16 c1 = load_acc_order(m.b1 + 16 * g);
+    const f32x16 c2 = load_acc_order(m.b2 + 16 * g);
+    const uint4 w3a = reinterpret_cast<const uint4 *>(m.w3 + 16 * g)[0];
+    const uint4 w3b = reinterpret_cast<const uint4 *>(m.w3 + 16 * g)[1];
+    const bf16x2 w3[8] = {__builtin_bit_cast(bf16x2, w3a.x), __builtin_bit_cast(bf16x2, w3a.y),
+                          __builtin_bit_cast(bf16x2, w3a.z), __builtin_bit_cast(bf16x2, w3a.w),
+                          __builtin_bit_cast(bf16x2, w3b.x), __builtin_bit_cast(bf16x2, w3b.y),
+                          __builtin_bit_cast(bf16x2, w3b.z), __builtin_bit_cast(bf16x2, w3b.w)};
 
     float z_own = 0.0f;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        const bool mine = (g == t);
-        const bf16x8 B1 = mine ? xo : zero;
-        const f32x4 c0 = {0.0f, 0.0f, 0.0f, 0.0f};
-        f32x4 h1a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(mine ? w1a0 : zero, B1, c0, 0, 0, 0);
-        f32x4 h1b = __builtin_amdgcn_mfma_f32_16x16x32_bf16(mine ? w1a1 : zero, B1, c0, 0, 0, 0);
-        bf16x8 B2;
-        B2[0] = (__bf16)fmaxf(h1a[0] + b1a.x, 0.0f);
-        B2[1] = (__bf16)fmaxf(h1a[1] + b1a.y, 0.0f);
-        B2[2] = (__bf16)fmaxf(h1a[2] + b1a.z, 0.0f);
-        B2[3] = (__bf16)fmaxf(h1a[3] + b1a.w, 0.0f);
-        B2[4] = (__bf16)fmaxf(h1b[0] + b1b.x, 0.0f);
-        B2[5] = (__bf16)fmaxf(h1b[1] + b1b.y, 0.0f);
-        B2[6] = (__bf16)fmaxf(h1b[2] + b1b.z, 0.0f);
-        B2[7] = (__bf16)fmaxf(h1b[3] + b1b.w, 0.0f);
-        f32x4 h2a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2a0, B2, c0, 0, 0, 0);
-        f32x4 h2b = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w2a1, B2, c0, 0, 0, 0);
+    for (int h = 0; h < 2; ++h) {
+        const bool mine = (g == h);
+        const f32x16 h1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(mine ? w1 : zero, mine ? xo : zero, c1, 0, 0, 0);
+        f32x16 h2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(load_bf16x8(m.w2 + ((0 * 2 + g) * 32 + j) * 8),
+                                                            relu_slots<0>(h1), c2, 0, 0, 0);
+        h2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(load_bf16x8(m.w2 + ((1 * 2 + g) * 32 + j) * 8),
+                                                     relu_slots<8>(h1), h2, 0, 0, 0);
         float part = 0.0f;
-        part += w3a.x * (float)(__bf16)fmaxf(h2a[0] + b2a.x, 0.0f);
-        part += w3a.y * (float)(__bf16)fmaxf(h2a[1] + b2a.y, 0.0f);
-        part += w3a.z * (float)(__bf16)fmaxf(h2a[2] + b2a.z, 0.0f);
-        part += w3a.w * (float)(__bf16)fmaxf(h2a[3] + b2a.w, 0.0f);
-        part += w3b.x * (float)(__bf16)fmaxf(h2b[0] + b2b.x, 0.0f);
-        part += w3b.y * (float)(__bf16)fmaxf(h2b[1] + b2b.y, 0.0f);
-        part += w3b.z * (float)(__bf16)fmaxf(h2b[2] + b2b.z, 0.0f);
-        part += w3b.w * (float)(__bf16)fmaxf(h2b[3] + b2b.w, 0.0f);
-        part += __shfl_xor(part, 16, 64);
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            part = __builtin_amdgcn_fdot2_f32_bf16(relu_bf16x2(h2[2 * q], h2[2 * q + 1]), w3[q], part, false);
         part += __shfl_xor(part, 32, 64);
-        if (mine) z_own = part + b3;
+        if (mine) z_own = part + m.b3[0];
     }
     return softplus_f(z_own);
 }
