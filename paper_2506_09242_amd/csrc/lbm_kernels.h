@@ -310,27 +310,24 @@ template <int Q, typename C, int MS>
 __device__ __forceinline__ void collide_closure(const C (&h)[Q], int tag, bool live, const StepParams &p,
                                                 C (&hs)[Q]) {
     constexpr int H = (Q - 1) / 2;
-    C drho = C(0), jx = C(0), jy = C(0), jz = C(0);
+    // moments from the pair sums and differences (the second moments see only
+    // the even parts, the momentum only the odd ones)
+    C drho = h[0], jx = C(0), jy = C(0), jz = C(0);
     C sxx = C(0), syy = C(0), szz = C(0), sxy = C(0), sxz = C(0), syz = C(0);
-    sfor<Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        using Vi = V<Q, i>;
-        drho += h[i];
-        if constexpr (Vi::x == 1) jx += h[i];
-        if constexpr (Vi::x == -1) jx -= h[i];
-        if constexpr (Vi::y == 1) jy += h[i];
-        if constexpr (Vi::y == -1) jy -= h[i];
-        if constexpr (Vi::z == 1) jz += h[i];
-        if constexpr (Vi::z == -1) jz -= h[i];
-        if constexpr (Vi::x != 0) sxx += h[i];
-        if constexpr (Vi::y != 0) syy += h[i];
-        if constexpr (Vi::z != 0) szz += h[i];
-        if constexpr (Vi::x * Vi::y == 1) sxy += h[i];
-        if constexpr (Vi::x * Vi::y == -1) sxy -= h[i];
-        if constexpr (Vi::x * Vi::z == 1) sxz += h[i];
-        if constexpr (Vi::x * Vi::z == -1) sxz -= h[i];
-        if constexpr (Vi::y * Vi::z == 1) syz += h[i];
-        if constexpr (Vi::y * Vi::z == -1) syz -= h[i];
+    C E[H + 1], O[H + 1];  // pair halves (h_k + h_k') / 2 and (h_k - h_k') / 2; h is not used again
+    sfor<H>([&](auto K) {
+        constexpr int k = decltype(K)::value + 1;
+        using Vk = V<Q, k>;
+        const C e = h[k] + h[k + H], o = h[k] - h[k + H];
+        E[k] = C(0.5) * e;
+        O[k] = C(0.5) * o;
+        drho += e;
+        if constexpr (Vk::x != 0) jx += C(Vk::x) * o, sxx += e;
+        if constexpr (Vk::y != 0) jy += C(Vk::y) * o, syy += e;
+        if constexpr (Vk::z != 0) jz += C(Vk::z) * o, szz += e;
+        if constexpr (Vk::x * Vk::y != 0) sxy += C(Vk::x * Vk::y) * e;
+        if constexpr (Vk::x * Vk::z != 0) sxz += C(Vk::x * Vk::z) * e;
+        if constexpr (Vk::y * Vk::z != 0) syz += C(Vk::y * Vk::z) * e;
     });
     const C Fx = (C)p.force[0], Fy = (C)p.force[1], Fz = (C)p.force[2];
     const C rho = (C)p.rho0 + drho;
@@ -370,12 +367,11 @@ __device__ __forceinline__ void collide_closure(const C (&h)[Q], int tag, bool l
         const C od = C(Vk::w) * C(3) * rho * cu;
         const C Fe = C(Vk::w) * (C(9) * cu * cF - C(3) * uF);
         const C Fo = C(Vk::w) * C(3) * cF;
-        const C hp = C(0.5) * (h[k] + h[k + H]);
-        const C hm = C(0.5) * (h[k] - h[k + H]);
+        const C hp = E[k], hm = O[k];
         const C A = g * Fe - w * (hp - ev);
         const C B = g * Fo - w * (hm - od);
-        hs[k] = h[k] + A + B;
-        hs[k + H] = h[k + H] + A - B;
+        hs[k] = (hp + hm) + A + B;
+        hs[k + H] = (hp - hm) + A - B;
     });
 }
 

@@ -43,7 +43,15 @@ __device__ __forceinline__ bf16x8 load_bf16x8(const uint16_t *p) {
     return __builtin_bit_cast(bf16x8, v);
 }
 
-__device__ __forceinline__ float softplus_f(float z) { return z > 20.0f ? z : log1pf(expf(z)); }
+// softplus(z) = ln(1 + e^z) from the hardware base-2 exponential and
+// logarithm (v_exp_f32, v_log_f32): ln 2 * log2(1 + t), t = 2^(z log2 e);
+// for z < -5, where 1 + t loses t's low bits, t (1 - t/2) instead (relative
+// error below t^2/3 < 2e-5); z itself above 15 (error below e^-15).
+__device__ __forceinline__ float softplus_f(float z) {
+    const float t = __builtin_amdgcn_exp2f(z * 1.44269504088896341f);
+    const float mid = 0.693147180559945309f * __builtin_amdgcn_logf(1.0f + t);
+    return z > 15.0f ? z : (z < -5.0f ? t * (1.0f - 0.5f * t) : mid);
+}
 
 // max(RNE_bf16(a), 0), max(RNE_bf16(b), 0): a negative BF16 pattern is a
 // negative 16-bit integer, so a signed max with 0 is the ReLU.
