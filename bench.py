@@ -118,11 +118,12 @@ def build_workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def alg_bytes_per_launch(tags, q, prec_bytes):
+def alg_bytes_per_launch(tags, q, prec_bytes, tagged=True):
     """Algorithmic HBM bytes of one collide-stream launch: every fluid node reads
-    and writes its Q populations once; every node's tag byte is read once."""
+    and writes its Q populations once; on a tagged lattice every node's tag byte
+    is read once (a lattice of one fluid model without walls reads no tags)."""
     fluid = int(np.isin(tags, FLUID_TAGS).sum())
-    return fluid * 2 * q * prec_bytes + tags.size, fluid
+    return fluid * 2 * q * prec_bytes + (tags.size if tagged else 0), fluid
 
 
 def run_dtype(tags, kw, rho, u, prec, steps, warmup, every, repeats=1, chunk=2000, label="", keep_rho=False,
@@ -211,7 +212,7 @@ def measure(tags, kw, rho, u, prec_names, args, label_prefix="", sample=None, ke
         prec = lbm.PREC_NAMES[pn]
         r = run_dtype(tags, kw, rho, u, prec, steps, args.warmup, args.every, args.repeats,
                       label=label_prefix + pn, keep_rho=keep_rho, sample=sample, parity_launches=10)
-        nbytes, nfluid = alg_bytes_per_launch(tags, kw["q"], lbm.PREC_BYTES[prec])
+        nbytes, nfluid = alg_bytes_per_launch(tags, kw["q"], lbm.PREC_BYTES[prec], "/uniform" not in r["variant"])
         launch_s = r["ms"] * 1e-3 / steps
         achieved = nbytes / launch_s / 1e9
         res = {"MLUPS": tags.size * steps / (r["ms"] * 1e-3) / 1e6,
@@ -431,7 +432,7 @@ def ceiling_mode(args):
             L = lbm.Lattice(tags, prec=prec, stream=stream, free_stream=True, **kw)
             L.init_equilibrium()
             L.step(4)
-            nb, _ = alg_bytes_per_launch(tags, kw["q"], lbm.PREC_BYTES[prec])
+            nb, _ = alg_bytes_per_launch(tags, kw["q"], lbm.PREC_BYTES[prec], "/uniform" not in L.variant)
             even = time_stream(stream, lambda: L.step(2), 10)  # an even + odd pair
             ev = [torch.cuda.Event(enable_timing=True) for _ in range(21)]
             ev[0].record(stream)
@@ -474,7 +475,7 @@ def slab_mode(args):
         s = lbm.PREC_BYTES[prec]
         dt = {1: torch.float32, 0: torch.float64, 2: torch.float16}[prec]
         bufs = [torch.empty(m * n * n, dtype=dt, device="cuda") for _ in range(2)]
-        nb, _ = alg_bytes_per_launch(tags, kw["q"], s)
+        nb, _ = alg_bytes_per_launch(tags, kw["q"], s, "/uniform" not in L.variant)
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(21)]
         ev[0].record(stream)
         for k in range(20):
