@@ -511,6 +511,8 @@ def main():
                     help="sample the enstrophy (Eq. 5 vorticity) after every chunk of the first run")
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD, choices=sorted(WORKLOADS))
     ap.add_argument("--dtypes", default="f32,f16s,f64", help="first one is the reported value")
+    ap.add_argument("--layout", choices=["rows", "bricks"], default=None,
+                    help="force the storage layout of the headline workload (default: the library's choice)")
     ap.add_argument("--no-extra", action="store_true", help="skip the extra cavity block")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=20)
@@ -567,6 +569,8 @@ def main():
 
     t_start = time.perf_counter()
     tags, kw, rho, u, wl_cfg = build_workload(args.workload)
+    if args.layout:
+        kw = dict(kw, layout=args.layout)
     print(f"# {args.workload}: inputs built in {time.perf_counter() - t_start:.1f} s", file=sys.stderr, flush=True)
     prec_names = [p.strip() for p in args.dtypes.split(",") if p.strip()]
     sample = (lambda L: L.enstrophy()) if args.enstrophy else None

@@ -118,7 +118,7 @@ typedef struct {
     int32_t nx, ny, nz;    /* lattice size, each >= 1, nx*ny*nz < 2^31          */
     int32_t q;             /* lbm_q                                              */
     int32_t prec;          /* lbm_prec                                           */
-    int32_t flags;         /* 0, or LBM_FLAG_FREE_STREAM                         */
+    int32_t flags;         /* 0, or LBM_FLAG_* bits below                        */
     double rho0;           /* reference density (offset and wall density), > 0  */
     double tau;            /* relaxation time, tau = 3 nu + 1/2, must be > 1/2  */
     double trt_lambda;     /* TRT magic parameter (3/16 for exact walls), > 0   */
@@ -136,6 +136,22 @@ typedef struct {
  * the streaming maps and for timing the memory access pattern of the step
  * without its arithmetic; not a physical model. */
 #define LBM_FLAG_FREE_STREAM 1
+
+/* Storage order of the nodes (tags, neighbour masks and the 4096-node blocks
+ * of the population array; the Structure-of-Array layout of Sec. 2.3 is kept
+ * inside each block).  Row layout: the natural order (z ny + y) nx + x.
+ * Brick layout: 16^3-node blocks of 4^3-node bricks, each brick x fastest, so
+ * that the 64-byte storage sectors a step reads and writes are 4 x 4 x 1 (FP32)
+ * patches rather than 16-node row segments: in a porous medium (Sec. 3.3)
+ * far fewer of them are mostly solid.  Default: the brick layout for tagged
+ * lattices with fewer than half of their nodes fluid and every side a multiple
+ * of 16, else the row layout (the variant name ends in "/bricks" for the
+ * brick layout).  LBM_FLAG_LAYOUT_BRICKS requests the brick layout (EINVAL
+ * unless every side is a multiple of 16); LBM_FLAG_LAYOUT_ROWS the row layout.
+ * Results do not depend on the layout (populations bitwise; reductions up to
+ * summation order); it is invisible through the API. */
+#define LBM_FLAG_LAYOUT_BRICKS 2
+#define LBM_FLAG_LAYOUT_ROWS 4
 
 /* FP64 domain reductions of the natural state at time `step`, over fluid nodes. */
 typedef struct {
@@ -194,7 +210,7 @@ void lbm_destroy(lbm_lattice *lat);
  * whose nx is a power of two in [64, 4096] uses row-form addressing (tx >= 64;
  * FP16 storage, or a tagged lattice with at least half of its nodes fluid; the
  * variant name then ends in "/rows").  EINVAL for other shapes. */
-lbm_status lbm_set_launch(lbm_lattice *lat, int tx, int ty);
+lbm_status lbm_set_launch(lbm_lattice *lat, int tx, int ty);  /* EUNSUPPORTED on brick-layout lattices */
 
 /* ---------------------------------------------------------- initial state */
 

@@ -58,6 +58,7 @@ struct lbm_lattice {
     bool tagged = true;
     int uniform_tag = LBM_TAG_BGK;
     int tx_log2 = 8;
+    bool brick = false;             // brick storage layout (see Layout)
     int tiles_x = 1, tiles_y = 1, n_tiles = 1;
     long long n_fluid = 0;
     bool failed = false;
@@ -143,7 +144,13 @@ lbm_status validate(const lbm_config *c) {
     if (n >= (1LL << 31)) return set_err(LBM_EINVAL, "nx*ny*nz = %lld exceeds 2^31 - 1", n);
     if (c->q != 19 && c->q != 27) return set_err(LBM_EINVAL, "q must be 19 or 27 (got %d)", c->q);
     if (c->prec < 0 || c->prec > 2) return set_err(LBM_EINVAL, "unknown precision %d", c->prec);
-    if ((c->flags & ~LBM_FLAG_FREE_STREAM) != 0) return set_err(LBM_EINVAL, "unknown flags 0x%x", c->flags);
+    if ((c->flags & ~(LBM_FLAG_FREE_STREAM | LBM_FLAG_LAYOUT_BRICKS | LBM_FLAG_LAYOUT_ROWS)) != 0)
+        return set_err(LBM_EINVAL, "unknown flags 0x%x", c->flags);
+    if ((c->flags & LBM_FLAG_LAYOUT_BRICKS) && (c->flags & LBM_FLAG_LAYOUT_ROWS))
+        return set_err(LBM_EINVAL, "LBM_FLAG_LAYOUT_BRICKS and LBM_FLAG_LAYOUT_ROWS exclude each other");
+    if ((c->flags & LBM_FLAG_LAYOUT_BRICKS) && (c->nx % 16 || c->ny % 16 || c->nz % 16))
+        return set_err(LBM_EINVAL, "the brick layout needs nx, ny, nz multiples of 16 (got %d x %d x %d)", c->nx, c->ny,
+                       c->nz);
     if (!(c->rho0 > 0.0) || !std::isfinite(c->rho0)) return set_err(LBM_EINVAL, "rho0 must be > 0");
     if (!(c->tau > 0.5) || !std::isfinite(c->tau)) return set_err(LBM_EINVAL, "tau must be > 1/2 (got %g)", c->tau);
     if (!(c->trt_lambda > 0.0) || !std::isfinite(c->trt_lambda)) return set_err(LBM_EINVAL, "trt_lambda must be > 0");
@@ -159,6 +166,14 @@ lbm_status validate(const lbm_config *c) {
 }
 
 void choose_tiles(lbm_lattice *L, int txl) {
+    if (L->brick) {
+        // 16 x 4 x 4 tiles of four 4^3 bricks (the brick layout's fixed tile)
+        L->tx_log2 = 4;
+        L->tiles_x = L->cfg.nx / 16;
+        L->tiles_y = L->cfg.ny / 4;
+        L->n_tiles = L->tiles_x * L->tiles_y * (L->cfg.nz / 4);
+        return;
+    }
     L->tx_log2 = txl;
     const int TX = 1 << txl, TY = 256 >> txl;
     L->tiles_x = (L->cfg.nx + TX - 1) / TX;
@@ -192,6 +207,7 @@ StepParams step_params(const lbm_lattice *L) {
     p.nx = c.nx;
     p.ny = c.ny;
     p.nz = c.nz;
+    p.lay = make_layout(L->brick ? 1 : 0, c.nx, c.ny);
     p.tiles_x = L->tiles_x;
     p.tiles_y = L->tiles_y;
     p.n_tiles = L->n_tiles;
@@ -205,7 +221,7 @@ StepParams step_params(const lbm_lattice *L) {
     const long long n_nodes = (long long)c.nx * c.ny * c.nz;
     const bool rows_pay = c.prec == LBM_F16S || (L->tagged && 2 * L->n_fluid >= n_nodes);
     p.row_log2 = -1;
-    if (rows_pay && L->tx_log2 >= 6 && c.nx >= 64 && c.nx <= (int)kBlockNodes &&
+    if (rows_pay && !L->brick && L->tx_log2 >= 6 && c.nx >= 64 && c.nx <= (int)kBlockNodes &&
         (c.nx & (c.nx - 1)) == 0) {
         int l = 0;
         while ((c.nx << l) < (int)kBlockNodes) ++l;
@@ -239,7 +255,7 @@ void name_variant(lbm_lattice *L) {
     const lbm_config &c = L->cfg;
     snprintf(L->variant, sizeof L->variant, "D3Q%d/%s/%s/%s%s", c.q,
              c.prec == LBM_F64 ? "f64" : (c.prec == LBM_F32 ? "f32" : "f16s"), ms,
-             L->tagged ? "tagged" : "uniform", step_params(L).row_log2 >= 0 ? "/rows" : "");
+             L->tagged ? "tagged" : "uniform", L->brick ? "/bricks" : (step_params(L).row_log2 >= 0 ? "/rows" : ""));
 }
 
 AuxParams aux_params(const lbm_lattice *L) {
@@ -249,6 +265,7 @@ AuxParams aux_params(const lbm_lattice *L) {
     a.nx = L->cfg.nx;
     a.ny = L->cfg.ny;
     a.nz = L->cfg.nz;
+    a.lay = make_layout(L->brick ? 1 : 0, L->cfg.nx, L->cfg.ny);
     a.parity = L->parity;
     a.rho0 = L->cfg.rho0;
     for (int k = 0; k < 3; ++k) a.force[k] = L->cfg.force[k];
@@ -465,7 +482,14 @@ static lbm_status create_impl(const lbm_config *cfg, const uint8_t *tags_host, v
     // mostly fluid domain); in solid-rich media (porous rock) they add more
     // scattered partial writes than they complete, so there only the even
     // step fills.
-    const bool odd_fill = tagged && count_fillers(tags_host, N, sector_log2(cfg->prec)) * 16 <= nf;
+    // Brick layout: on request, or by default for solid-rich tagged lattices
+    // (fewer than half the nodes fluid) whose sides are multiples of 16: there
+    // the 4 x 4 x 1 sectors of the brick order hold fluid far more often than
+    // the 16-node row segments of the row order.
+    const bool dims16 = cfg->nx % 16 == 0 && cfg->ny % 16 == 0 && cfg->nz % 16 == 0;
+    const bool brick = (cfg->flags & LBM_FLAG_LAYOUT_BRICKS) ||
+                       (!(cfg->flags & LBM_FLAG_LAYOUT_ROWS) && dims16 && tagged && 2 * nf < N);
+    const bool odd_fill = tagged && !brick && count_fillers(tags_host, N, sector_log2(cfg->prec)) * 16 <= nf;
 
     const size_t need_bytes = lbm_population_bytes(cfg);
     if (pops_dev) {
@@ -485,6 +509,7 @@ static lbm_status create_impl(const lbm_config *cfg, const uint8_t *tags_host, v
     L->ms = ms;
     L->tagged = tagged;
     L->uniform_tag = only;
+    L->brick = brick;
     choose_tiles(L, default_txl(cfg->nx));
     name_variant(L);
 
@@ -552,15 +577,43 @@ static lbm_status create_impl(const lbm_config *cfg, const uint8_t *tags_host, v
             return bail(set_err(LBM_ENOMEM, "hipMalloc of neighbour masks failed"));
         }
     }
-    e = hipMemcpyAsync(L->d_tags, tags_host, (size_t)N, hipMemcpyHostToDevice, L->stream);
+    // tags on the device in storage order
+    const Layout lay = make_layout(brick ? 1 : 0, cfg->nx, cfg->ny);
+    std::vector<uint8_t> stags;
+    const uint8_t *up = tags_host;
+    if (brick) {
+        try {
+            stags.resize((size_t)N);
+        } catch (...) {
+            return bail(set_err(LBM_ENOMEM, "host allocation failed"));
+        }
+        for (int z = 0; z < cfg->nz; ++z)
+            for (int y = 0; y < cfg->ny; ++y) {
+                const uint8_t *row = tags_host + ((long long)z * cfg->ny + y) * cfg->nx;
+                const int base = lay.z(z) + lay.y(y);
+                for (int x = 0; x < cfg->nx; ++x) stags[(size_t)(base + lay.x(x))] = row[x];
+            }
+        up = stags.data();
+    }
+    e = hipMemcpyAsync(L->d_tags, up, (size_t)N, hipMemcpyHostToDevice, L->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(L->d_wall, cfg->wall_velocity, 16 * 3 * sizeof(double), hipMemcpyHostToDevice, L->stream);
     if (e == hipSuccess && L->tagged)
-        e = cfg->q == 19 ? launch_build_mask<19>(L->d_tags, cfg->nx, cfg->ny, cfg->nz, sector_log2(cfg->prec),
+        e = cfg->q == 19 ? launch_build_mask<19>(L->d_tags, cfg->nx, cfg->ny, cfg->nz, lay, sector_log2(cfg->prec),
                                                  odd_fill, L->d_mask, L->stream)
-                         : launch_build_mask<27>(L->d_tags, cfg->nx, cfg->ny, cfg->nz, sector_log2(cfg->prec),
+                         : launch_build_mask<27>(L->d_tags, cfg->nx, cfg->ny, cfg->nz, lay, sector_log2(cfg->prec),
                                                  odd_fill, L->d_mask, L->stream);
-    if (e == hipSuccess && L->tagged) e = launch_tile_classify(step_params(L), L->d_tile_tag, L->stream);
+    // wave classes: row layout only (a brick wave and its halo are one model
+    // too rarely in the solid-rich media the brick layout is for)
+    if (e == hipSuccess && L->tagged) {
+        if (brick)
+            e = hipMemsetAsync(L->d_tile_tag, 0, (size_t)max_tiles * 4 * sizeof(int), L->stream);
+        else
+            e = launch_tile_classify(step_params(L), L->d_tile_tag, L->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
+    if (e != hipSuccess) return bail(lbmd_fail_hip(nullptr, e, "tag upload"));
+    if (brick) std::vector<uint8_t>().swap(stags);
     if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
     if (e != hipSuccess) return bail(lbmd_fail_hip(nullptr, e, "tag upload"));
     *out = L;
@@ -597,6 +650,7 @@ extern "C" void lbm_destroy(lbm_lattice *lat) {
 
 extern "C" lbm_status lbm_set_launch(lbm_lattice *lat, int tx, int ty) {
     CHECK_HANDLE(lat);
+    if (lat->brick) return set_err(LBM_EUNSUPPORTED, "the brick layout has a fixed 16 x 4 x 4 tile");
     int l = -1;
     for (int k = 5; k <= 8; ++k)
         if (tx == (1 << k)) l = k;

@@ -58,12 +58,37 @@ __device__ __forceinline__ bool is_fluid_tag(int t) { return t >= 1 && t <= 10; 
 constexpr int kBlockLog2 = 12;
 constexpr long long kBlockNodes = 1ll << kBlockLog2;
 
-// Element index of population 0 of node n (0 <= n < 2^31).
+// Element index of population 0 of the node with storage index n (0 <= n < 2^31).
 template <int Q>
 __device__ __forceinline__ long long pop_base(int n) {
     const unsigned b = (unsigned)n >> kBlockLog2;
     return (long long)((unsigned long long)b * (unsigned)(Q << kBlockLog2)) + (n & (int)(kBlockNodes - 1));
 }
+// Storage order of the nodes.  Every per-node array on the device (the
+// populations' blocks, tags, neighbour masks) is indexed by a storage index
+// s = lay_z(z) + lay_y(y) + lay_x(x), separable in the three coordinates:
+//  - row layout (brick == 0): s = (z ny + y) nx + x, the natural order;
+//  - brick layout (brick == 1, nx, ny, nz multiples of 16): the lattice is cut
+//    into 16^3 blocks (4096 nodes, block index (z/16 * nby + y/16) * nbx +
+//    x/16), each block into 64 bricks of 4^3 nodes (brick index
+//    (z/4 % 4) 16 + (y/4 % 4) 4 + x/4 % 4) and each brick ordered x fastest;
+//    a 64-byte sector of FP32 storage is then a 4 x 4 x 1 patch instead of 16
+//    nodes of one row, which a porous medium fills with fluid far more often.
+struct Layout {
+    int brick, nx, nxy, nbx, nbxy;
+    __host__ __device__ int x(int v) const { return brick ? ((v >> 4) << 12) | (((v >> 2) & 3) << 6) | (v & 3) : v; }
+    __host__ __device__ int y(int v) const {
+        return brick ? (v >> 4) * (nbx << 12) + ((((v >> 2) & 3) << 8) | ((v & 3) << 2)) : v * nx;
+    }
+    __host__ __device__ int z(int v) const {
+        return brick ? (v >> 4) * (nbxy << 12) + ((((v >> 2) & 3) << 10) | ((v & 3) << 4)) : v * nxy;
+    }
+    __host__ __device__ int at(int vx, int vy, int vz) const { return z(vz) + y(vy) + x(vx); }
+};
+__host__ __device__ inline Layout make_layout(int brick, int nx, int ny) {
+    return Layout{brick, nx, nx * ny, nx >> 4, (nx >> 4) * (ny >> 4)};
+}
+
 // Element offset of slot i from population 0 of the same node.
 __device__ __forceinline__ constexpr long long slot_off(int i) { return (long long)i << kBlockLog2; }
 

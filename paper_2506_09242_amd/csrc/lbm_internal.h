@@ -11,6 +11,7 @@
 #include <cstdint>
 
 #include "lbm.h"
+#include "lbm_device.h"
 
 namespace lbmd {
 
@@ -70,7 +71,10 @@ struct StepParams {
     double *partials;         // [NRED][partial_stride] per-tile reduction partials
     long long partial_stride; // tiles per reduction slot in `partials`
     int nx, ny, nz;
-    int tiles_x, tiles_y;     // tile grid in x and y (z: one plane per tile row)
+    Layout lay;               // storage order of the nodes (row or brick layout)
+    int tiles_x, tiles_y;     // tile grid in x and y (row layout: one plane per tile
+                              // row; brick layout: 16 x 4 x 4 tiles, tiles_y counts y
+                              // and the tile rows run over z / 4)
     int n_tiles;              // tiles_x * tiles_y * nz
     int tiles_per_xcd;        // ceil(n_tiles / 8)
     int tx_log2;              // tile width = 1 << tx_log2, height = 256 >> tx_log2
@@ -96,6 +100,7 @@ struct AuxParams {
     void *pops;
     const uint8_t *tags;
     int nx, ny, nz;
+    Layout lay;               // storage order of tags and populations
     int parity;               // layout parity of the state (0: natural)
     int shifted;              // gathers/scatters of h_i = f_i - w_i rho0 (not f_i)
     double rho0;
@@ -116,8 +121,8 @@ hipError_t launch_step(const StepParams &p, int ms, bool tagged, int mode, int p
 template <int Q>
 // sector_log2: log2 of the nodes per 64-byte storage sector in the lattice's
 // precision; odd_fill: also mark the odd-step filler targets.
-hipError_t launch_build_mask(const uint8_t *tags, int nx, int ny, int nz, int sector_log2, int odd_fill,
-                             uint32_t *mask, hipStream_t s);
+hipError_t launch_build_mask(const uint8_t *tags, int nx, int ny, int nz, Layout lay, int sector_log2,
+                             int odd_fill, uint32_t *mask, hipStream_t s);
 template <int Q, int P>
 hipError_t launch_init(const AuxParams &a, hipStream_t s);
 template <int Q, int P>

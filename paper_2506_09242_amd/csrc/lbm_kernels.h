@@ -616,24 +616,44 @@ __global__ __launch_bounds__(256) void k_collide_stream(StepParams p) {
     const int L = (wg & 7) * p.tiles_per_xcd + (wg >> 3);
     if (L >= p.n_tiles) return;  // uniform for the block
 
-    const int txl = p.tx_log2;
-    const int TX = 1 << txl, TY = 256 >> txl;
-    const int tix = L % p.tiles_x;
-    const int rem = L / p.tiles_x;
-    const int tiy = rem % p.tiles_y;
-    const int z = rem / p.tiles_y;
-    const int lx = threadIdx.x & (TX - 1), ly = threadIdx.x >> txl;
-    const int x = (tix << txl) + lx, y = tiy * TY + ly;
     const int nx = p.nx, ny = p.ny, nz = p.nz;
+    int x, y, z;
+    int xo[3], yo[3], zo[3];  // storage-index terms of the neighbours, index 1 + c for c in {-1, 0, 1}
+    if (!p.lay.brick) {
+        // row layout: a tile of (1 << tx_log2) x (256 >> tx_log2) nodes of one plane
+        const int txl = p.tx_log2;
+        const int TX = 1 << txl, TY = 256 >> txl;
+        const int tix = L % p.tiles_x;
+        const int rem = L / p.tiles_x;
+        const int tiy = rem % p.tiles_y;
+        z = rem / p.tiles_y;
+        x = (tix << txl) + (threadIdx.x & (TX - 1));
+        y = tiy * TY + (threadIdx.x >> txl);
+        // neighbour offsets with periodic wrap
+        const bool in = (x < nx) && (y < ny);
+        const int xc = in ? x : 0, yc = in ? y : 0;
+        xo[0] = xc == 0 ? nx - 1 : xc - 1, xo[1] = xc, xo[2] = xc + 1 == nx ? 0 : xc + 1;
+        yo[0] = (yc == 0 ? ny - 1 : yc - 1) * nx, yo[1] = yc * nx, yo[2] = (yc + 1 == ny ? 0 : yc + 1) * nx;
+        const int nxy = nx * ny;
+        zo[0] = (z == 0 ? nz - 1 : z - 1) * nxy, zo[1] = z * nxy, zo[2] = (z + 1 == nz ? 0 : z + 1) * nxy;
+    } else {
+        // brick layout: a 16 x 4 x 4 tile, wave w the 4^3 brick at x offset 4 w,
+        // lane l the node (l % 4, l / 4 % 4, l / 16) of that brick (every axis a
+        // multiple of 16: no partial tiles)
+        const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+        const int tix = L % p.tiles_x;
+        const int rem = L / p.tiles_x;
+        const int tiy = rem % p.tiles_y;
+        x = tix * 16 + w * 4 + (l & 3);
+        y = tiy * 4 + ((l >> 2) & 3);
+        z = (rem / p.tiles_y) * 4 + (l >> 4);
+        const Layout &ly = p.lay;
+        xo[0] = ly.x(x == 0 ? nx - 1 : x - 1), xo[1] = ly.x(x), xo[2] = ly.x(x + 1 == nx ? 0 : x + 1);
+        yo[0] = ly.y(y == 0 ? ny - 1 : y - 1), yo[1] = ly.y(y), yo[2] = ly.y(y + 1 == ny ? 0 : y + 1);
+        zo[0] = ly.z(z == 0 ? nz - 1 : z - 1), zo[1] = ly.z(z), zo[2] = ly.z(z + 1 == nz ? 0 : z + 1);
+    }
     const bool active = (x < nx) && (y < ny);
-
-    // Neighbour offsets with periodic wrap; index 1 + c for c in {-1, 0, 1}.
-    const int xc = active ? x : 0, yc = active ? y : 0;
-    const int xo[3] = {xc == 0 ? nx - 1 : xc - 1, xc, xc + 1 == nx ? 0 : xc + 1};
-    const int yo[3] = {(yc == 0 ? ny - 1 : yc - 1) * nx, yc * nx, (yc + 1 == ny ? 0 : yc + 1) * nx};
-    const int nxy = nx * ny;
-    const int zo[3] = {(z == 0 ? nz - 1 : z - 1) * nxy, z * nxy, (z + 1 == nz ? 0 : z + 1) * nxy};
-    const int n = zo[1] + yo[1] + xo[1];
+    const int n = zo[1] + yo[1] + xo[1];  // storage index of the node
 
     // Node class.  Waves whose 64 nodes and their one-node halo are a single
     // fluid model (the interior of a walled domain) need nothing; the other
@@ -691,9 +711,10 @@ __global__ __launch_bounds__(256) void k_collide_stream(StepParams p) {
         const S *rp[3][3] = {};
         unsigned xb[3] = {0u, 0u, 0u};
         if constexpr (RF) {
-            const int ys = __builtin_amdgcn_readfirstlane(y);
+            // row layout only: y and z are uniform over the wave
+            const int ys = __builtin_amdgcn_readfirstlane(y), zs = __builtin_amdgcn_readfirstlane(z);
             const int yv[3] = {ys == 0 ? ny - 1 : ys - 1, ys, ys + 1 == ny ? 0 : ys + 1};
-            const int zv[3] = {z == 0 ? nz - 1 : z - 1, z, z + 1 == nz ? 0 : z + 1};
+            const int zv[3] = {zs == 0 ? nz - 1 : zs - 1, zs, zs + 1 == nz ? 0 : zs + 1};
             const int rl = p.row_log2;
             sfor<3>([&](auto DZ) {
                 sfor<3>([&](auto DY) {
@@ -878,16 +899,18 @@ __global__ __launch_bounds__(256) void k_collide_stream(StepParams p) {
 }
 
 // Neighbour mask of every node (see kMask*): wall bits, moving-wall flag and
-// the node's own fluid tag (0 for non-fluid nodes).
+// the node's own fluid tag (0 for non-fluid nodes); tags and masks in storage
+// order (lay).
 template <int Q>
-__global__ __launch_bounds__(256) void k_build_mask(const uint8_t *tags, int nx, int ny, int nz, int sector_log2,
-                                                    int odd_fill, uint32_t *mask) {
+__global__ __launch_bounds__(256) void k_build_mask(const uint8_t *tags, int nx, int ny, int nz, Layout lay,
+                                                    int sector_log2, int odd_fill, uint32_t *mask) {
     const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
     const long long N = (long long)nx * ny * nz;
     if (t >= N) return;
     const int x = (int)(t % nx), y = (int)((t / nx) % ny), z = (int)(t / ((long long)nx * ny));
-    auto fluid_at = [&](int gx, int gy, int gz) { return is_fluid_tag(tags[((long long)gz * ny + gy) * nx + gx]); };
-    const int own = tags[t];
+    auto fluid_at = [&](int gx, int gy, int gz) { return is_fluid_tag(tags[lay.at(gx, gy, gz)]); };
+    const long long s = lay.at(x, y, z);
+    const int own = tags[s];
     uint32_t m = 0;
     if (is_fluid_tag(own)) {
         m = (uint32_t)own << kMaskTagShift;
@@ -896,7 +919,7 @@ __global__ __launch_bounds__(256) void k_build_mask(const uint8_t *tags, int nx,
             if constexpr (i > 0) {
                 using Vi = V<Q, i>;
                 const int gx = wrap_idx(x + Vi::x, nx), gy = wrap_idx(y + Vi::y, ny), gz = wrap_idx(z + Vi::z, nz);
-                const int tn = tags[((long long)gz * ny + gy) * nx + gx];
+                const int tn = tags[lay.at(gx, gy, gz)];
                 if (!is_fluid_tag(tn)) m |= 1u << i;
                 if (tn >= LBM_TAG_WALL0) m |= 1u << kMaskMovingBit;
             }
@@ -904,7 +927,7 @@ __global__ __launch_bounds__(256) void k_build_mask(const uint8_t *tags, int nx,
     } else {
         // filler: a non-fluid node in a storage sector that also holds fluid nodes
         const long long g = 1ll << sector_log2;
-        const long long a = t & ~(g - 1), b = a + g < N ? a + g : N;
+        const long long a = s & ~(g - 1), b = a + g < N ? a + g : N;
         bool any = false;
         for (long long k = a; k < b; ++k) any |= is_fluid_tag(tags[k]);
         if (any) {
@@ -920,10 +943,17 @@ __global__ __launch_bounds__(256) void k_build_mask(const uint8_t *tags, int nx,
             }
         }
     }
-    mask[t] = m;
+    mask[s] = m;
 }
 
 // ------------------------------------------------------------- helpers
+
+// Storage index of the node with natural index n = (z ny + y) nx + x.
+__device__ __forceinline__ int storage_index(const AuxParams &a, long long n) {
+    if (!a.lay.brick) return (int)n;
+    const int x = (int)(n % a.nx), y = (int)((n / a.nx) % a.ny), z = (int)(n / ((long long)a.nx * a.ny));
+    return a.lay.at(x, y, z);
+}
 
 // Equilibrium initialisation (FP64 arithmetic, rounded once to storage).
 template <int Q, int P>
@@ -931,7 +961,7 @@ __global__ __launch_bounds__(256) void k_init(AuxParams a) {
     using S = typename Prec<P>::S;
     const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
     if (t >= a.count) return;
-    const long long n = a.cell0 + t;
+    const int n = storage_index(a, a.cell0 + t);
     if (!is_fluid_tag(a.tags[n])) return;
     const double rho = a.in_rho ? a.in_rho[t] : a.rho0;
     const double ux = a.in_u ? a.in_u[t] : 0.0;
@@ -945,25 +975,27 @@ __global__ __launch_bounds__(256) void k_init(AuxParams a) {
         using Vi = V<Q, i>;
         const double cu = Vi::x * ux + Vi::y * uy + Vi::z * uz;
         const double heq = Vi::w * (drho + rho * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
-        f[pop_base<Q>((int)n) + slot_off(i)] = (S)heq;
+        f[pop_base<Q>(n) + slot_off(i)] = (S)heq;
     });
 }
 
-// Natural state of node n: h_i(n) for every i (slot map of the layout parity).
+// Natural state of the node with natural index n: h_i(n) for every i (slot
+// map of the layout parity).
 template <int Q, int P>
 __device__ __forceinline__ void load_natural(const AuxParams &a, long long n, double (&fo)[Q]) {
     using S = typename Prec<P>::S;
     const S *f = static_cast<const S *>(a.pops);
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const int x = (int)(n % nx), y = (int)((n / nx) % ny), z = (int)(n / ((long long)nx * ny));
+    const int sn = a.lay.at(x, y, z);
     sfor<Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         using Vi = V<Q, i>;
-        long long off = pop_base<Q>((int)n) + slot_off(i);
+        long long off = pop_base<Q>(sn) + slot_off(i);
         if (a.parity != 0 && i != 0) {
             const int sx = wrap_idx(x - Vi::x, nx), sy = wrap_idx(y - Vi::y, ny), sz = wrap_idx(z - Vi::z, nz);
-            const long long src = ((long long)sz * ny + sy) * nx + sx;
-            if (is_fluid_tag(a.tags[src])) off = pop_base<Q>((int)src) + slot_off(Vi::opp);
+            const int src = a.lay.at(sx, sy, sz);
+            if (is_fluid_tag(a.tags[src])) off = pop_base<Q>(src) + slot_off(Vi::opp);
         }
         fo[i] = a.shifted ? (double)f[off] : (double)f[off] + Vi::w * a.rho0;
     });
@@ -974,7 +1006,7 @@ __global__ __launch_bounds__(256) void k_gather(AuxParams a, int gmode) {
     const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
     if (t >= a.count) return;
     const long long n = gmode == G_CELLS ? a.cells[t] : a.cell0 + t;
-    const bool fl = is_fluid_tag(a.tags[n]);
+    const bool fl = is_fluid_tag(a.tags[storage_index(a, n)]);
     if (gmode == G_FIELDS) a.shifted = 0;
     double fo[Q];
     if (fl) {
@@ -1010,14 +1042,14 @@ __global__ __launch_bounds__(256) void k_scatter(AuxParams a) {
     using S = typename Prec<P>::S;
     const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
     if (t >= a.count) return;
-    const long long n = a.cell0 + t;
+    const int n = storage_index(a, a.cell0 + t);
     if (!is_fluid_tag(a.tags[n])) return;
     S *f = static_cast<S *>(a.pops);
     sfor<Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         using Vi = V<Q, i>;
         const double v = a.in_f[(long long)i * a.count + t];
-        f[pop_base<Q>((int)n) + slot_off(i)] = (S)(a.shifted ? v : v - Vi::w * a.rho0);
+        f[pop_base<Q>(n) + slot_off(i)] = (S)(a.shifted ? v : v - Vi::w * a.rho0);
     });
 }
 
@@ -1031,7 +1063,7 @@ __global__ __launch_bounds__(256) void k_face(AuxParams a, int face, int unpack,
     const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
     if (t >= nxy) return;
     const int plane = face == 0 ? 0 : a.nz - 1;
-    const int n = (int)((long long)plane * nxy + t);
+    const int n = storage_index(a, (long long)plane * nxy + t);
     S *f = static_cast<S *>(a.pops);
     S *b = static_cast<S *>(buf);
     const long long base = pop_base<Q>(n);
@@ -1119,10 +1151,10 @@ hipError_t launch_step(const StepParams &p, int ms, bool tagged, int mode, int p
 }
 
 template <int Q>
-hipError_t launch_build_mask(const uint8_t *tags, int nx, int ny, int nz, int sector_log2, int odd_fill,
-                             uint32_t *mask, hipStream_t s) {
+hipError_t launch_build_mask(const uint8_t *tags, int nx, int ny, int nz, Layout lay, int sector_log2,
+                             int odd_fill, uint32_t *mask, hipStream_t s) {
     const long long N = (long long)nx * ny * nz;
-    k_build_mask<Q><<<(unsigned)((N + 255) / 256), 256, 0, s>>>(tags, nx, ny, nz, sector_log2, odd_fill, mask);
+    k_build_mask<Q><<<(unsigned)((N + 255) / 256), 256, 0, s>>>(tags, nx, ny, nz, lay, sector_log2, odd_fill, mask);
     return hipGetLastError();
 }
 

@@ -3,5 +3,5 @@
 
 namespace lbmd {
 LBMD_INSTANTIATE(19, 0)
-template hipError_t launch_build_mask<19>(const uint8_t *, int, int, int, int, int, uint32_t *, hipStream_t);
+template hipError_t launch_build_mask<19>(const uint8_t *, int, int, int, Layout, int, int, uint32_t *, hipStream_t);
 }  // namespace lbmd

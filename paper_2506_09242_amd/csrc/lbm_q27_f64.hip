@@ -3,5 +3,5 @@
 
 namespace lbmd {
 LBMD_INSTANTIATE(27, 0)
-template hipError_t launch_build_mask<27>(const uint8_t *, int, int, int, int, int, uint32_t *, hipStream_t);
+template hipError_t launch_build_mask<27>(const uint8_t *, int, int, int, Layout, int, int, uint32_t *, hipStream_t);
 }  // namespace lbmd

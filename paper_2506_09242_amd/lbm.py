@@ -28,6 +28,8 @@ MLP_NPARAMS = 1359
 PREC_NAMES = {"f64": LBM_F64, "f32": LBM_F32, "f16s": LBM_F16S}
 PREC_BYTES = {LBM_F64: 8, LBM_F32: 4, LBM_F16S: 2}
 LBM_FLAG_FREE_STREAM = 1
+LBM_FLAG_LAYOUT_BRICKS = 2
+LBM_FLAG_LAYOUT_ROWS = 4
 
 
 class LbmConfig(C.Structure):
@@ -208,20 +210,23 @@ class Lattice:
     x = nx-1, densities (x = 0, x = nx-1)); stream: a torch stream or raw
     handle (default: torch's current stream); torch_buffer: let torch own the
     population array (lbm_create_on_buffer); free_stream: collision switched off
-    (LBM_FLAG_FREE_STREAM).
+    (LBM_FLAG_FREE_STREAM); layout: None (the library's default), "rows"
+    (LBM_FLAG_LAYOUT_ROWS) or "bricks" (LBM_FLAG_LAYOUT_BRICKS).
     """
 
     def __init__(self, tags: np.ndarray, q=19, prec=LBM_F64, tau=0.8, rho0=1.0, trt_lambda=3.0 / 16.0,
                  smag_cs=0.0, force=(0.0, 0.0, 0.0), wall_velocity=None, stream=None, torch_buffer=False,
-                 bc_velocity=(0.0, 0.0, 0.0), bc_density=(1.0, 1.0), free_stream=False):
+                 bc_velocity=(0.0, 0.0, 0.0), bc_density=(1.0, 1.0), free_stream=False, layout=None):
         tags = np.ascontiguousarray(tags, dtype=np.uint8)
         assert tags.ndim == 3
         nz, ny, nx = tags.shape
         self.shape = (nz, ny, nx)
         self.N = nx * ny * nz
         self.q = q
+        flags = (LBM_FLAG_FREE_STREAM if free_stream else 0) | {None: 0, "rows": LBM_FLAG_LAYOUT_ROWS,
+                                                                 "bricks": LBM_FLAG_LAYOUT_BRICKS}[layout]
         self.cfg = make_config(nx, ny, nz, q, prec, tau, rho0, trt_lambda, smag_cs, force, wall_velocity,
-                               bc_velocity, bc_density, LBM_FLAG_FREE_STREAM if free_stream else 0)
+                               bc_velocity, bc_density, flags)
         self.tags = tags
         self._stream = _stream_handle(stream)
         self._buf = None

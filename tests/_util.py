@@ -12,12 +12,13 @@ def fluid_mask(tags):
     return np.isin(tags, FLUID)
 
 
-def make_pair(tags, q=19, prec=lbm.LBM_F64, rho=None, u=None, mlp=None, **kw):
-    """Oracle and HIP lattices with the same configuration and initial state."""
+def make_pair(tags, q=19, prec=lbm.LBM_F64, rho=None, u=None, mlp=None, layout=None, **kw):
+    """Oracle and HIP lattices with the same configuration and initial state
+    (layout: the HIP lattice's storage layout, None for its default)."""
     nz, ny, nx = tags.shape
     o = oracle.Oracle(nx, ny, nz, q=q, tags=tags, mlp=mlp, **kw)
     o.init_equilibrium(rho, u)
-    L = lbm.Lattice(tags, q=q, prec=prec, **kw)
+    L = lbm.Lattice(tags, q=q, prec=prec, layout=layout, **kw)
     if mlp is not None:
         L.set_mlp(mlp)
     L.init_equilibrium(rho, u)

@@ -71,7 +71,8 @@ def _create(cfg, tags):
 @pytest.mark.parametrize("field,value,needle", [
     ("tau", 0.5, "tau"), ("tau", 0.3, "tau"), ("q", 15, "q must"), ("prec", 7, "precision"),
     ("rho0", 0.0, "rho0"), ("trt_lambda", -1.0, "trt_lambda"), ("smag_cs", -0.1, "smag_cs"),
-    ("flags", 2, "flags"), ("flags", -1, "flags"), ("nx", 0, "size"),
+    ("flags", 8, "flags"), ("flags", -1, "flags"), ("flags", 2, "multiples of 16"), ("flags", 6, "exclude"),
+    ("nx", 0, "size"),
 ])
 def test_create_rejects_bad_config(field, value, needle):
     cfg = lbm.make_config(4, 4, 4)

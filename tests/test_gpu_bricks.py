@@ -1,0 +1,170 @@
+"""The brick storage layout (16^3 blocks of 4^3 bricks; LBM_FLAG_LAYOUT_BRICKS)
+on the GPU: against the FP64 oracle, bitwise against the row layout, and
+through every entry point that addresses the storage (init, gathers, state
+read/write, cell reads, reductions, z-face pack/unpack, free streaming).
+
+Solid-rich lattices whose sides are multiples of 16 take it by default; the
+tests also force it (and the row layout) with the layout flags."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2506_09242_amd import inputs, lbm
+
+from _util import fluid_mask, make_pair, max_rel_pop_error, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    lbm.lib()
+    yield
+
+
+def _tags(kind, nx, ny, nz):
+    if kind == "walls":
+        return inputs.random_tags(nx, ny, nz, seed=31, solid_frac=0.55, wall_frac=0.05)
+    if kind == "mixed":
+        return inputs.random_tags(nx, ny, nz, seed=32, solid_frac=0.3, wall_frac=0.05,
+                                  fluid_tags=(inputs.TAG_BGK, inputs.TAG_TRT, inputs.TAG_SMAG, inputs.TAG_REG,
+                                              inputs.TAG_RR))
+    if kind == "porous":
+        assert nx == ny == nz
+        return inputs.porous_tags(nx, porosity=0.20, ell=4.0, seed=42)
+    raise KeyError(kind)
+
+
+KW = dict(tau=0.8, trt_lambda=3.0 / 16.0, smag_cs=0.1, force=(1e-5, 2e-6, 0.0),
+          wall_velocity=[(0.05, 0.0, 0.0), (0.0, 0.02, 0.01)])
+
+
+@pytest.mark.parametrize("q,kind,shape,steps", [
+    (19, "walls", (32, 48, 16), 37),
+    (27, "walls", (16, 32, 32), 24),
+    (19, "mixed", (48, 16, 32), 31),
+    (27, "mixed", (32, 32, 16), 18),
+    (19, "porous", (32, 32, 32), 51),
+])
+def test_bricks_fp64_match_oracle(q, kind, shape, steps):
+    """Every fluid population within 1e-12 of the oracle after an odd and an
+    even number of steps; the lattice takes the brick layout."""
+    nx, ny, nz = shape
+    tags = _tags(kind, nx, ny, nz)
+    rho, u = inputs.random_fields(nx, ny, nz, seed=5)
+    o, L = make_pair(tags, q=q, prec=lbm.LBM_F64, rho=rho, u=u, layout="bricks", **KW)
+    assert L.variant.endswith("/bricks"), L.variant
+    for n in (steps, 1):
+        L.step(n)
+        o.run(n)
+        err = max_rel_pop_error(L.read_populations(), o.f, tags)
+        print(kind, q, shape, L.time, L.variant, "max rel pop err", err, flush=True)
+        assert err <= TOL
+    r_g, u_g = L.read_fields()
+    r_o, u_o = o.fields()
+    fl = fluid_mask(tags)
+    assert rel_l2(r_g[fl], r_o[fl]) <= TOL and rel_l2(u_g[:, fl], u_o[:, fl]) <= 1e-10
+    m, m_o = L.reduce(), o.moments()
+    assert m["n_fluid"] == m_o["n_fluid"]
+    assert abs(m["mass_delta"] - m_o["mass_delta"]) <= TOL * m["n_fluid"]
+    L.close()
+
+
+@pytest.mark.parametrize("prec", [lbm.LBM_F64, lbm.LBM_F32, lbm.LBM_F16S])
+@pytest.mark.parametrize("q,kind", [(19, "walls"), (27, "mixed"), (19, "porous")])
+def test_bricks_bitwise_equal_rows(prec, q, kind):
+    """Same lattice in the brick and the row layout: populations bitwise equal
+    after odd and even step counts (the node update does not depend on the
+    storage order); reductions equal up to summation order."""
+    n = 32
+    tags = _tags(kind, n, n, n)
+    rho, u = inputs.random_fields(n, n, n, seed=6)
+    out = {}
+    for layout in ("bricks", "rows"):
+        L = lbm.Lattice(tags, q=q, prec=prec, layout=layout, **KW)
+        L.init_equilibrium(rho, u)
+        s1 = L.step_reduce(13, 4)
+        f13 = L.read_state()
+        L.step(8)
+        out[layout] = (L.variant, f13, L.read_state(), s1, L.reduce())
+        L.close()
+    vb, vr = out["bricks"][0], out["rows"][0]
+    assert vb.endswith("/bricks") and not vr.endswith("/bricks"), (vb, vr)
+    assert np.array_equal(out["bricks"][1], out["rows"][1])
+    assert np.array_equal(out["bricks"][2], out["rows"][2])
+    for a, b in zip(out["bricks"][3] + [out["bricks"][4]], out["rows"][3] + [out["rows"][4]]):
+        assert a["step"] == b["step"] and a["n_nonfinite"] == b["n_nonfinite"] == 0
+        assert abs(a["mass_delta"] - b["mass_delta"]) <= 1e-12 * a["n_fluid"]
+        assert abs(a["kinetic_energy"] / b["kinetic_energy"] - 1.0) <= 1e-11
+
+
+def test_layout_choice_and_entry_points():
+    """Default layout: bricks for a solid-rich lattice with sides multiple of 16,
+    rows for a mostly fluid one and for sides that are not; the flags force
+    either; bricks reject lbm_set_launch; read_cells, checkpoint and write
+    round trips agree with the row layout bitwise."""
+    porous = _tags("porous", 32, 32, 32)
+    assert lbm.Lattice(porous, q=19, tau=1.0).variant.endswith("/bricks")
+    assert not lbm.Lattice(porous, q=19, tau=1.0, layout="rows").variant.endswith("/bricks")
+    assert not lbm.Lattice(inputs.cavity_tags(32), q=19, tau=0.8).variant.endswith("/bricks")
+    assert not lbm.Lattice(inputs.porous_tags(40, 0.2, 4.0, 42), q=19, tau=1.0).variant.endswith("/bricks")
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.Lattice(inputs.all_fluid(24, 16, 16), q=19, layout="bricks")
+    assert e.value.status == lbm.LBM_EINVAL
+    Lb = lbm.Lattice(porous, q=19, prec=lbm.LBM_F32, tau=1.0, force=(1e-5, 0, 0))
+    with pytest.raises(lbm.LbmError) as e:
+        Lb.set_launch(64, 4)
+    assert e.value.status == lbm.LBM_EUNSUPPORTED
+    Lr = lbm.Lattice(porous, q=19, prec=lbm.LBM_F32, tau=1.0, force=(1e-5, 0, 0), layout="rows")
+    rho, u = inputs.random_fields(32, 32, 32, seed=7)
+    for L in (Lb, Lr):
+        L.init_equilibrium(rho, u)
+        L.step(9)
+    cells = np.array([0, 5, 32 * 32 * 32 - 1, 1234, 17 * 1024 + 3 * 32 + 30], dtype=np.int64)
+    assert np.array_equal(Lb.read_cells(cells), Lr.read_cells(cells))
+    sb = Lb.read_state()
+    assert np.array_equal(sb, Lr.read_state())
+    # write the state back into the brick lattice (odd time): it must read back bitwise
+    Lb.write_state(sb, 9)
+    assert np.array_equal(Lb.read_state(), sb)
+    Lb.step(4)
+    Lr.step(4)
+    assert np.array_equal(Lb.read_state(), Lr.read_state())
+    Lb.close()
+    Lr.close()
+
+
+@pytest.mark.parametrize("q", [19, 27])
+def test_bricks_free_streaming_matches_oracle(q):
+    """Collision switched off: the brick layout's streaming and bounce-back maps
+    against the oracle's free streaming (7 steps, walls and moving walls).  With
+    no collision a population that bounces off moving walls again and again
+    keeps losing 6 w rho0 c.u_w; slow walls here keep every population above
+    half its weight, so the relative comparison stays meaningful."""
+    tags = _tags("walls", 32, 16, 16)
+    rho, u = inputs.random_fields(32, 16, 16, seed=8)
+    nz, ny, nx = tags.shape
+    kw = dict(KW, wall_velocity=[(0.01, 0.0, 0.0), (0.0, 0.005, 0.005)])
+    o = oracle.Oracle(nx, ny, nz, q=q, tags=tags, free_streaming=True, **kw)
+    o.init_equilibrium(rho, u)
+    L = lbm.Lattice(tags, q=q, prec=lbm.LBM_F64, free_stream=True, layout="bricks", **kw)
+    L.init_equilibrium(rho, u)
+    L.step(7)
+    o.run(7)
+    fl = fluid_mask(tags)
+    print("free streaming q", q, "min f", o.f[:, fl].min(), flush=True)
+    assert max_rel_pop_error(L.read_populations(), o.f, tags) <= TOL
+    L.close()
+
+
+@pytest.mark.parametrize("prec", [lbm.LBM_F32, lbm.LBM_F16S])
+def test_bricks_slab_faces(prec):
+    """z-slab face pack / unpack on brick-layout slabs (16 and 32 planes of a
+    16 x 32 x 48 D3Q27 lattice) reproduce the whole row-layout lattice bitwise."""
+    from test_gpu_slab import run_slabs
+    variants = run_slabs(prec, 27, (16, 32), 16, 32, layout="bricks")
+    assert all(v.endswith("/bricks") for v in variants), variants

@@ -7,7 +7,8 @@ phase with their own collision model, boundaries, forcing and kernel variant:
     the wall waves take the row-form addresses);
   - porous medium (Sec. 3.3 shape, synthetic rock): D3Q19 TRT with the magic
     parameter 3/16, tau = 1, body force 1e-5 along x, a Gaussian-random-field
-    solid (correlation length 8) at porosity 0.20, 2000 steps;
+    solid (correlation length 8) at porosity 0.20, 2000 steps (solid-rich with
+    sides a multiple of 16: the brick storage layout);
   - Taylor-Green vortex (Sec. 3.1, Eqs. (1)-(4)): D3Q27 BGK + Smagorinsky
     (C_s = 0.1), u0 = 0.05, Re = 1600 on the reference length N / 2 pi,
     500 steps.
@@ -86,8 +87,8 @@ def gpu():
 EXPECT_VARIANT = {
     "cavity": {lbm.LBM_F64: "D3Q19/f64/bgk/tagged/rows", lbm.LBM_F32: "D3Q19/f32/bgk/tagged/rows",
                lbm.LBM_F16S: "D3Q19/f16s/bgk/tagged/rows"},
-    "porous": {lbm.LBM_F64: "D3Q19/f64/trt/tagged", lbm.LBM_F32: "D3Q19/f32/trt/tagged",
-               lbm.LBM_F16S: "D3Q19/f16s/trt/tagged/rows"},
+    "porous": {lbm.LBM_F64: "D3Q19/f64/trt/tagged/bricks", lbm.LBM_F32: "D3Q19/f32/trt/tagged/bricks",
+               lbm.LBM_F16S: "D3Q19/f16s/trt/tagged/bricks"},
     "tgv": {lbm.LBM_F64: "D3Q27/f64/bgk+smag/uniform", lbm.LBM_F32: "D3Q27/f32/bgk+smag/uniform",
             lbm.LBM_F16S: "D3Q27/f16s/bgk+smag/uniform/rows"},
 }

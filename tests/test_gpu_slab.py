@@ -77,16 +77,10 @@ def _exchange(slabs, bufs, before):
             s.face_unpack(1, bufs[(j + 1) % m][1])
 
 
-@pytest.mark.parametrize("prec", [lbm.LBM_F64, lbm.LBM_F32, lbm.LBM_F16S])
-@pytest.mark.parametrize("q,heights,nx", [(19, (7, 6, 7), 21), (27, (5, 1, 6), 64), (27, (4, 4), 21)])
-def test_slabs_with_face_exchange_equal_whole_lattice(prec, q, heights, nx):
-    """Slabs of unequal heights (one a single plane) stacked along z, each its own
-    periodic lattice, exchanging faces around every odd step: every population of
-    every slab equals the whole lattice's bit for bit at even times (natural
-    layout).  Three slabs make the exchange a rotation, not a swap, so a face
-    sent the wrong way fails; nx = 64 takes the FP16 row form."""
+def run_slabs(prec, q, heights, nx, ny, layout=None):
+    """Slabs stacked along z exchanging faces around every odd step against the
+    whole lattice: every population bitwise equal at even times 2 and 12."""
     import torch
-    ny = 10
     nz = sum(heights)
     tag = inputs.TAG_SMAG if q == 27 else inputs.TAG_BGK
     kw = dict(q=q, prec=prec, tau=0.56, smag_cs=0.1, force=(1e-5, 0.0, -2e-6))
@@ -95,7 +89,7 @@ def test_slabs_with_face_exchange_equal_whole_lattice(prec, q, heights, nx):
     whole.init_equilibrium(rho, u)
     slabs, z0 = [], 0
     for h in heights:
-        s = lbm.Lattice(inputs.all_fluid(nx, ny, h, tag), **kw)
+        s = lbm.Lattice(inputs.all_fluid(nx, ny, h, tag), layout=layout, **kw)
         s.init_equilibrium(rho[z0:z0 + h], u[:, z0:z0 + h])
         slabs.append(s)
         z0 += h
@@ -116,6 +110,18 @@ def test_slabs_with_face_exchange_equal_whole_lattice(prec, q, heights, nx):
             parts = np.concatenate([s.read_state() for s in slabs], axis=1)
             assert np.array_equal(parts, fw), whole.time
     torch.cuda.synchronize()
+    return [s.variant for s in slabs]
+
+
+@pytest.mark.parametrize("prec", [lbm.LBM_F64, lbm.LBM_F32, lbm.LBM_F16S])
+@pytest.mark.parametrize("q,heights,nx", [(19, (7, 6, 7), 21), (27, (5, 1, 6), 64), (27, (4, 4), 21)])
+def test_slabs_with_face_exchange_equal_whole_lattice(prec, q, heights, nx):
+    """Slabs of unequal heights (one a single plane) stacked along z, each its own
+    periodic lattice, exchanging faces around every odd step: every population of
+    every slab equals the whole lattice's bit for bit at even times (natural
+    layout).  Three slabs make the exchange a rotation, not a swap, so a face
+    sent the wrong way fails; nx = 64 takes the FP16 row form."""
+    run_slabs(prec, q, heights, nx, 10)
 
 
 def test_face_populations_and_errors():
