@@ -477,18 +477,22 @@ static lbm_status create_impl(const lbm_config *cfg, const uint8_t *tags_host, v
             n_models++;
             only = t;
         }
-    const bool tagged = !(nf == N && n_models == 1);
-    // Odd-step filler stores pay off where filler nodes are few (walls of a
-    // mostly fluid domain); in solid-rich media (porous rock) they add more
-    // scattered partial writes than they complete, so there only the even
-    // step fills.
+    const bool one_model = nf == N && n_models == 1;
     // Brick layout: on request, or by default for solid-rich tagged lattices
     // (fewer than half the nodes fluid) whose sides are multiples of 16: there
     // the 4 x 4 x 1 sectors of the brick order hold fluid far more often than
     // the 16-node row segments of the row order.
     const bool dims16 = cfg->nx % 16 == 0 && cfg->ny % 16 == 0 && cfg->nz % 16 == 0;
     const bool brick = (cfg->flags & LBM_FLAG_LAYOUT_BRICKS) ||
-                       (!(cfg->flags & LBM_FLAG_LAYOUT_ROWS) && dims16 && tagged && 2 * nf < N);
+                       (!(cfg->flags & LBM_FLAG_LAYOUT_ROWS) && dims16 && !one_model && 2 * nf < N);
+    // Lattices of one fluid model without walls run the untagged kernels
+    // (no tags or masks read), unless they take the brick layout, which only
+    // the tagged kernels implement.
+    const bool tagged = !one_model || brick;
+    // Odd-step filler stores pay off where filler nodes are few (walls of a
+    // mostly fluid domain); in solid-rich media (porous rock) they add more
+    // scattered partial writes than they complete, so there only the even
+    // step fills.
     const bool odd_fill = tagged && !brick && count_fillers(tags_host, N, sector_log2(cfg->prec)) * 16 <= nf;
 
     const size_t need_bytes = lbm_population_bytes(cfg);

@@ -604,10 +604,14 @@ __device__ __forceinline__ void collide_node(const C (&h)[Q], int tag, bool live
 // covering a tile of (1 << tx_log2) x (256 >> tx_log2) nodes of one z-plane.
 // Wall handling selects addresses rather than branching around loads, so the
 // Q loads of a thread are all in flight together.
-template <int Q, int P, int MS, bool TAGGED, int MODE, int PARITY, bool ROWS>
+template <int Q, int P, int MS, bool TAGGED, int MODE, int PARITY, int ADDR>
 __global__ __launch_bounds__(256) void k_collide_stream(StepParams p) {
     using S = typename Prec<P>::S;
     using C = typename Prec<P>::C;
+    // ADDR 0: row layout, node-form addresses; 1: row layout, row-form
+    // addresses; 2: brick layout (tagged kernels), node-form addresses
+    constexpr bool ROWS = ADDR == 1;
+    constexpr bool BRICK = ADDR == 2;
 
     // XCD-aware tile order: hardware deals workgroups round-robin over the 8
     // XCDs, so workgroup w runs on XCD w % 8; give each XCD a contiguous run
@@ -619,7 +623,7 @@ __global__ __launch_bounds__(256) void k_collide_stream(StepParams p) {
     const int nx = p.nx, ny = p.ny, nz = p.nz;
     int x, y, z;
     int xo[3], yo[3], zo[3];  // storage-index terms of the neighbours, index 1 + c for c in {-1, 0, 1}
-    if (!p.lay.brick) {
+    if constexpr (!BRICK) {
         // row layout: a tile of (1 << tx_log2) x (256 >> tx_log2) nodes of one plane
         const int txl = p.tx_log2;
         const int TX = 1 << txl, TY = 256 >> txl;
@@ -711,10 +715,9 @@ __global__ __launch_bounds__(256) void k_collide_stream(StepParams p) {
         const S *rp[3][3] = {};
         unsigned xb[3] = {0u, 0u, 0u};
         if constexpr (RF) {
-            // row layout only: y and z are uniform over the wave
-            const int ys = __builtin_amdgcn_readfirstlane(y), zs = __builtin_amdgcn_readfirstlane(z);
+            const int ys = __builtin_amdgcn_readfirstlane(y);
             const int yv[3] = {ys == 0 ? ny - 1 : ys - 1, ys, ys + 1 == ny ? 0 : ys + 1};
-            const int zv[3] = {zs == 0 ? nz - 1 : zs - 1, zs, zs + 1 == nz ? 0 : zs + 1};
+            const int zv[3] = {z == 0 ? nz - 1 : z - 1, z, z + 1 == nz ? 0 : z + 1};
             const int rl = p.row_log2;
             sfor<3>([&](auto DZ) {
                 sfor<3>([&](auto DY) {
@@ -1092,14 +1095,14 @@ __global__ __launch_bounds__(256) void k_face(AuxParams a, int face, int unpack,
 // and the odd step lose with any cap.
 constexpr unsigned kEvenLdsCap = 41u << 10;
 
-template <int Q, int P, int MS, bool TG, int MODE, bool ROWS>
+template <int Q, int P, int MS, bool TG, int MODE, int ADDR>
 static hipError_t launch_step_rows(const StepParams &p, int parity, hipStream_t s) {
     const dim3 grid(8 * p.tiles_per_xcd), block(256);
-    constexpr unsigned lds_even = (ROWS && TG && P != 2) ? kEvenLdsCap : 0u;
+    constexpr unsigned lds_even = (ADDR == 1 && TG && P != 2) ? kEvenLdsCap : 0u;
     if (parity == 0)
-        k_collide_stream<Q, P, MS, TG, MODE, 0, ROWS><<<grid, block, lds_even, s>>>(p);
+        k_collide_stream<Q, P, MS, TG, MODE, 0, ADDR><<<grid, block, lds_even, s>>>(p);
     else
-        k_collide_stream<Q, P, MS, TG, MODE, 1, ROWS><<<grid, block, 0, s>>>(p);
+        k_collide_stream<Q, P, MS, TG, MODE, 1, ADDR><<<grid, block, 0, s>>>(p);
     return hipGetLastError();
 }
 
@@ -1111,11 +1114,14 @@ static hipError_t launch_step_rows(const StepParams &p, int parity, hipStream_t 
 // slower than the node form).
 template <int Q, int P, int MS, bool TG, int MODE>
 static hipError_t launch_step_par(const StepParams &p, int parity, hipStream_t s) {
+    if constexpr (TG) {
+        if (p.lay.brick) return launch_step_rows<Q, P, MS, TG, MODE, 2>(p, parity, s);
+    }
     constexpr bool kRows = P == 2 || TG;
     if constexpr (kRows) {
-        if (p.row_log2 >= 0) return launch_step_rows<Q, P, MS, TG, MODE, true>(p, parity, s);
+        if (p.row_log2 >= 0) return launch_step_rows<Q, P, MS, TG, MODE, 1>(p, parity, s);
     }
-    return launch_step_rows<Q, P, MS, TG, MODE, false>(p, parity, s);
+    return launch_step_rows<Q, P, MS, TG, MODE, 0>(p, parity, s);
 }
 
 template <int Q, int P, int MS, bool TG>
