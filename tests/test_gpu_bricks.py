@@ -36,11 +36,20 @@ def _tags(kind, nx, ny, nz):
     if kind == "porous":
         assert nx == ny == nz
         return inputs.porous_tags(nx, porosity=0.20, ell=4.0, seed=42)
+    if kind == "open":
+        # rock between a pressure inlet (x = 0) and a pressure outlet (x = nx - 1)
+        assert ny == nz
+        t = inputs.porous_tags(ny, porosity=0.25, ell=4.0, seed=43)
+        t = np.concatenate([t] * (nx // ny), axis=2) if nx > ny else t[:, :, :nx]
+        t = np.ascontiguousarray(t)
+        t[:, :, 0] = inputs.TAG_PIN
+        t[:, :, -1] = inputs.TAG_POUT
+        return t
     raise KeyError(kind)
 
 
 KW = dict(tau=0.8, trt_lambda=3.0 / 16.0, smag_cs=0.1, force=(1e-5, 2e-6, 0.0),
-          wall_velocity=[(0.05, 0.0, 0.0), (0.0, 0.02, 0.01)])
+          wall_velocity=[(0.05, 0.0, 0.0), (0.0, 0.02, 0.01)], bc_density=(1.004, 1.0))
 
 
 @pytest.mark.parametrize("q,kind,shape,steps", [
@@ -49,6 +58,7 @@ KW = dict(tau=0.8, trt_lambda=3.0 / 16.0, smag_cs=0.1, force=(1e-5, 2e-6, 0.0),
     (19, "mixed", (48, 16, 32), 31),
     (27, "mixed", (32, 32, 16), 18),
     (19, "porous", (32, 32, 32), 51),
+    (27, "open", (64, 32, 32), 23),
 ])
 def test_bricks_fp64_match_oracle(q, kind, shape, steps):
     """Every fluid population within 1e-12 of the oracle after an odd and an
@@ -75,7 +85,7 @@ def test_bricks_fp64_match_oracle(q, kind, shape, steps):
 
 
 @pytest.mark.parametrize("prec", [lbm.LBM_F64, lbm.LBM_F32, lbm.LBM_F16S])
-@pytest.mark.parametrize("q,kind", [(19, "walls"), (27, "mixed"), (19, "porous")])
+@pytest.mark.parametrize("q,kind", [(19, "walls"), (27, "mixed"), (19, "porous"), (19, "open")])
 def test_bricks_bitwise_equal_rows(prec, q, kind):
     """Same lattice in the brick and the row layout: populations bitwise equal
     after odd and even step counts (the node update does not depend on the
