@@ -292,7 +292,7 @@ def test_row_form_matches_node_form(prec, q, nx, ny, nz, kind):
         kw = dict(tau=0.6, wall_velocity=[(0.1, 0, 0)])
     rho, u = inputs.random_fields(nx, ny, nz, seed=7)
     outs, sers, names = [], [], []
-    for tx in (32, 64, 256):
+    for tx in (32, 64, 128, 256):
         L = lbm.Lattice(tags, q=q, prec=prec, **kw)
         L.set_launch(tx, 256 // tx)
         names.append(L.variant)
