@@ -332,23 +332,36 @@ __global__ __launch_bounds__(256) void k_finalize2(const double *stage1, int nb,
     }
 }
 
-// One block per tile: load the tile's tags with a one-node halo (periodic)
-// and report the tag if every one of them is the same fluid tag, else 0.
+// One block per tile; wave w of the block classifies the 64 nodes that wave w
+// of the step kernel updates: -1 when none of them is fluid or a filler (every
+// mask zero), else, in the row layout, their fluid tag when they and their
+// one-node halo (periodic) all carry that one tag, else 0.  Brick waves are
+// never given a tag (a brick and its halo are one model too rarely in the
+// solid-rich media the brick layout is for).
 __global__ __launch_bounds__(256) void k_tile_classify(StepParams p, int *out) {
-    // One block per tile; wave w of the block classifies the 64 nodes that wave
-    // w of the step kernel updates, together with their one-node halo.
     const int L = blockIdx.x;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int tix = L % p.tiles_x, rem = L / p.tiles_x;
+    const int tiy = rem % p.tiles_y;
+    if (p.lay.brick) {
+        // the step kernel's brick mapping: every axis a multiple of 16, no partial tiles
+        const int x = tix * 16 + w * 4 + (lane & 3), y = tiy * 4 + ((lane >> 2) & 3);
+        const int z = (rem / p.tiles_y) * 4 + (lane >> 4);
+        const bool none = __ballot(p.mask[p.lay.at(x, y, z)] != 0u) == 0ull;
+        if (lane == 0) out[(long long)L * 4 + w] = none ? -1 : 0;
+        return;
+    }
     const int txl = p.tx_log2;
     const int TX = 1 << txl;
-    const int tix = L % p.tiles_x, rem = L / p.tiles_x;
-    const int tiy = rem % p.tiles_y, z = rem / p.tiles_y;
+    const int z = rem / p.tiles_y;
     const int x0 = tix * TX, y0 = tiy * (256 >> txl);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int t = threadIdx.x;
     const int x = x0 + (t & (TX - 1)), y = y0 + (t >> txl);
     const bool in = x < p.nx && y < p.ny;
     const int xc = in ? x : x0 < p.nx ? x0 : 0, yc = in ? y : y0 < p.ny ? y0 : 0;
-    const int first = p.tags[((long long)z * p.ny + yc) * p.nx + xc];
+    const long long own = ((long long)z * p.ny + yc) * p.nx + xc;
+    const int first = p.tags[own];
+    const bool none = __ballot(in && p.mask[own] != 0u) == 0ull;
     // the wave's first in-range node sets the reference tag
     const unsigned long long act = __ballot(in);
     const int src = act ? __ffsll((long long)act) - 1 : 0;
@@ -365,8 +378,7 @@ __global__ __launch_bounds__(256) void k_tile_classify(StepParams p, int *out) {
     }
     // a wave is plain when every in-range lane saw only the reference tag
     const bool all = __ballot(in && !same) == 0ull && same;
-    if (lane == 0) out[(long long)L * 4 + w] = all ? ref : 0;
-    (void)lane;
+    if (lane == 0) out[(long long)L * 4 + w] = all ? ref : (none ? -1 : 0);
 }
 
 hipError_t launch_tile_classify(const StepParams &p, int *out, hipStream_t s) {
@@ -607,14 +619,8 @@ static lbm_status create_impl(const lbm_config *cfg, const uint8_t *tags_host, v
                                                  odd_fill, L->d_mask, L->stream)
                          : launch_build_mask<27>(L->d_tags, cfg->nx, cfg->ny, cfg->nz, lay, sector_log2(cfg->prec),
                                                  odd_fill, L->d_mask, L->stream);
-    // wave classes: row layout only (a brick wave and its halo are one model
-    // too rarely in the solid-rich media the brick layout is for)
-    if (e == hipSuccess && L->tagged) {
-        if (brick)
-            e = hipMemsetAsync(L->d_tile_tag, 0, (size_t)max_tiles * 4 * sizeof(int), L->stream);
-        else
-            e = launch_tile_classify(step_params(L), L->d_tile_tag, L->stream);
-    }
+    // wave classes (from the tags and the masks just built)
+    if (e == hipSuccess && L->tagged) e = launch_tile_classify(step_params(L), L->d_tile_tag, L->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
     if (e != hipSuccess) return bail(lbmd_fail_hip(nullptr, e, "tag upload"));
     if (brick) std::vector<uint8_t>().swap(stags);

@@ -65,7 +65,9 @@ struct StepParams {
     const uint8_t *tags;      // device tags (TAGGED variants)
     const int *tile_tag;      // per tile and wave ([tile][4]): the fluid tag when the
                               // wave's 64 nodes and their one-node halo are that one
-                              // model, else 0 (32-bit words: one scalar load per wave)
+                              // model, -1 when none of its nodes is fluid or a filler
+                              // (the wave has nothing to do), else 0 (32-bit words:
+                              // one scalar load per wave)
     const uint32_t *mask;     // per-node neighbour mask (TAGGED variants)
     const double *wall_u;     // [16][3] moving-wall velocities (device)
     double *partials;         // [NRED][partial_stride] per-tile reduction partials

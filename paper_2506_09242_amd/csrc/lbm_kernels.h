@@ -660,22 +660,27 @@ __global__ __launch_bounds__(256) void k_collide_stream(StepParams p) {
     const int n = zo[1] + yo[1] + xo[1];  // storage index of the node
 
     // Node class.  Waves whose 64 nodes and their one-node halo are a single
-    // fluid model (the interior of a walled domain) need nothing; the other
-    // waves read each node's precomputed neighbour mask (wave-uniform branch).
+    // fluid model (the interior of a walled domain) need nothing; waves with no
+    // fluid or filler node (solid rock) skip the update; the other waves read
+    // each node's precomputed neighbour mask (wave-uniform branches).
     S *__restrict__ f = static_cast<S *>(p.pops);
     const long long pb = pop_base<Q>(n);
     int tag = p.uniform_tag;
     uint32_t wall = 0;   // bit i: node x + c_i is not fluid
     bool moving = false; // some neighbour is a moving wall
     bool plain = !TAGGED;
+    bool skip = false;
     if constexpr (TAGGED) {
         // wave-uniform entry read through the constant address space (scalar load)
         typedef const __attribute__((address_space(4))) int const_int;
         const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
         const int tile_tag = ((const_int *)p.tile_tag)[L * 4 + wave];
-        if (tile_tag != 0) {
+        if (tile_tag > 0) {
             tag = tile_tag;
             plain = true;
+        } else if (tile_tag < 0) {
+            tag = 0;
+            skip = true;
         } else {
             const uint32_t m = active ? p.mask[n] : 0u;
             wall = m & kMaskWalls;
@@ -872,6 +877,8 @@ __global__ __launch_bounds__(256) void k_collide_stream(StepParams p) {
     using no = std::false_type;
     if constexpr (ROWS && !TAGGED) {
         update(yes{}, no{});
+    } else if (skip) {
+        // no fluid or filler node: nothing to load, update or store
     } else if constexpr (ROWS && P == 2) {
         if (plain) update(yes{}, no{});
         else update(yes{}, yes{});
