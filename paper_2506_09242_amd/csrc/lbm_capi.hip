@@ -167,7 +167,8 @@ lbm_status validate(const lbm_config *c) {
 
 void choose_tiles(lbm_lattice *L, int txl) {
     if (L->brick) {
-        // 16 x 4 x 4 tiles of four 4^3 bricks (the brick layout's fixed tile)
+        // tiles of four listed 4^3 bricks (the brick layout's fixed tile); the
+        // count is set when the list of bricks holding fluid is built
         L->tx_log2 = 4;
         L->tiles_x = L->cfg.nx / 16;
         L->tiles_y = L->cfg.ny / 4;
@@ -332,25 +333,15 @@ __global__ __launch_bounds__(256) void k_finalize2(const double *stage1, int nb,
     }
 }
 
-// One block per tile; wave w of the block classifies the 64 nodes that wave w
-// of the step kernel updates: -1 when none of them is fluid or a filler (every
-// mask zero), else, in the row layout, their fluid tag when they and their
-// one-node halo (periodic) all carry that one tag, else 0.  Brick waves are
-// never given a tag (a brick and its halo are one model too rarely in the
-// solid-rich media the brick layout is for).
+// Row layout.  One block per tile; wave w of the block classifies the 64 nodes
+// that wave w of the step kernel updates: their fluid tag when they and their
+// one-node halo (periodic) all carry that one tag, else -1 when none of them
+// is fluid or a filler (every mask zero), else 0.
 __global__ __launch_bounds__(256) void k_tile_classify(StepParams p, int *out) {
     const int L = blockIdx.x;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int tix = L % p.tiles_x, rem = L / p.tiles_x;
     const int tiy = rem % p.tiles_y;
-    if (p.lay.brick) {
-        // the step kernel's brick mapping: every axis a multiple of 16, no partial tiles
-        const int x = tix * 16 + w * 4 + (lane & 3), y = tiy * 4 + ((lane >> 2) & 3);
-        const int z = (rem / p.tiles_y) * 4 + (lane >> 4);
-        const bool none = __ballot(p.mask[p.lay.at(x, y, z)] != 0u) == 0ull;
-        if (lane == 0) out[(long long)L * 4 + w] = none ? -1 : 0;
-        return;
-    }
     const int txl = p.tx_log2;
     const int TX = 1 << txl;
     const int z = rem / p.tiles_y;
@@ -596,6 +587,7 @@ static lbm_status create_impl(const lbm_config *cfg, const uint8_t *tags_host, v
     // tags on the device in storage order
     const Layout lay = make_layout(brick ? 1 : 0, cfg->nx, cfg->ny);
     std::vector<uint8_t> stags;
+    std::vector<int> blist;
     const uint8_t *up = tags_host;
     if (brick) {
         try {
@@ -610,6 +602,22 @@ static lbm_status create_impl(const lbm_config *cfg, const uint8_t *tags_host, v
                 for (int x = 0; x < cfg->nx; ++x) stags[(size_t)(base + lay.x(x))] = row[x];
             }
         up = stags.data();
+        // The bricks that hold fluid, in storage order (bricks are 64 consecutive
+        // storage indices), four to a tile, -1 padding the last tile.  A brick
+        // without fluid has no filler either (its sectors hold no fluid), so no
+        // wave is launched for it.
+        try {
+            blist.reserve((size_t)(N / 64) + 4);
+        } catch (...) {
+            return bail(set_err(LBM_ENOMEM, "host allocation failed"));
+        }
+        for (long long b = 0; b < N / 64; ++b) {
+            bool any = false;
+            for (int k = 0; k < 64 && !any; ++k) any = is_fluid_tag(stags[(size_t)(b * 64 + k)]);
+            if (any) blist.push_back((int)b);
+        }
+        while (blist.size() % 4) blist.push_back(-1);
+        L->n_tiles = (int)(blist.size() / 4);
     }
     e = hipMemcpyAsync(L->d_tags, up, (size_t)N, hipMemcpyHostToDevice, L->stream);
     if (e == hipSuccess)
@@ -619,8 +627,14 @@ static lbm_status create_impl(const lbm_config *cfg, const uint8_t *tags_host, v
                                                  odd_fill, L->d_mask, L->stream)
                          : launch_build_mask<27>(L->d_tags, cfg->nx, cfg->ny, cfg->nz, lay, sector_log2(cfg->prec),
                                                  odd_fill, L->d_mask, L->stream);
-    // wave classes (from the tags and the masks just built)
-    if (e == hipSuccess && L->tagged) e = launch_tile_classify(step_params(L), L->d_tile_tag, L->stream);
+    // wave classes (from the tags and the masks just built), or the brick list
+    if (e == hipSuccess && L->tagged) {
+        if (brick)
+            e = hipMemcpyAsync(L->d_tile_tag, blist.data(), blist.size() * sizeof(int), hipMemcpyHostToDevice,
+                               L->stream);
+        else
+            e = launch_tile_classify(step_params(L), L->d_tile_tag, L->stream);
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(L->stream);
     if (e != hipSuccess) return bail(lbmd_fail_hip(nullptr, e, "tag upload"));
     if (brick) std::vector<uint8_t>().swap(stags);

@@ -46,7 +46,7 @@ __device__ __forceinline__ void sfor(F &&f) {
     sfor_impl(f, std::make_integer_sequence<int, N>{});
 }
 
-__device__ __forceinline__ bool is_fluid_tag(int t) { return t >= 1 && t <= 10; }
+__host__ __device__ inline bool is_fluid_tag(int t) { return t >= 1 && t <= 10; }
 
 // Population layout (blocked structure of arrays).  Node indices are grouped
 // in blocks of kBlockNodes consecutive nodes; a block stores its Q slots one

@@ -63,21 +63,22 @@ struct MlpDev {
 struct StepParams {
     void *pops;               // population array (blocked layout, see pop_base)
     const uint8_t *tags;      // device tags (TAGGED variants)
-    const int *tile_tag;      // per tile and wave ([tile][4]): the fluid tag when the
+    const int *tile_tag;      // per tile and wave ([tile][4], 32-bit words: one scalar
+                              // load per wave).  Row layout: the fluid tag when the
                               // wave's 64 nodes and their one-node halo are that one
                               // model, -1 when none of its nodes is fluid or a filler
-                              // (the wave has nothing to do), else 0 (32-bit words:
-                              // one scalar load per wave)
+                              // (the wave has nothing to do), else 0.  Brick layout:
+                              // the storage index / 64 of the wave's brick (the bricks
+                              // holding fluid, in storage order), -1 past the last
     const uint32_t *mask;     // per-node neighbour mask (TAGGED variants)
     const double *wall_u;     // [16][3] moving-wall velocities (device)
     double *partials;         // [NRED][partial_stride] per-tile reduction partials
     long long partial_stride; // tiles per reduction slot in `partials`
     int nx, ny, nz;
     Layout lay;               // storage order of the nodes (row or brick layout)
-    int tiles_x, tiles_y;     // tile grid in x and y (row layout: one plane per tile
-                              // row; brick layout: 16 x 4 x 4 tiles, tiles_y counts y
-                              // and the tile rows run over z / 4)
-    int n_tiles;              // tiles_x * tiles_y * nz
+    int tiles_x, tiles_y;     // tile grid in x and y (row layout; one plane per tile row)
+    int n_tiles;              // row layout: tiles_x * tiles_y * nz; brick layout: the
+                              // bricks holding fluid / 4, rounded up
     int tiles_per_xcd;        // ceil(n_tiles / 8)
     int tx_log2;              // tile width = 1 << tx_log2, height = 256 >> tx_log2
     int row_log2;             // log2(rows per 4096-node block) when whole rows tile the

@@ -622,6 +622,7 @@ __global__ __launch_bounds__(256) void k_collide_stream(StepParams p) {
 
     const int nx = p.nx, ny = p.ny, nz = p.nz;
     int x, y, z;
+    bool brick_none = false;  // brick layout: a padding wave past the last listed brick
     int xo[3], yo[3], zo[3];  // storage-index terms of the neighbours, index 1 + c for c in {-1, 0, 1}
     if constexpr (!BRICK) {
         // row layout: a tile of (1 << tx_log2) x (256 >> tx_log2) nodes of one plane
@@ -641,17 +642,23 @@ __global__ __launch_bounds__(256) void k_collide_stream(StepParams p) {
         const int nxy = nx * ny;
         zo[0] = (z == 0 ? nz - 1 : z - 1) * nxy, zo[1] = z * nxy, zo[2] = (z + 1 == nz ? 0 : z + 1) * nxy;
     } else {
-        // brick layout: a 16 x 4 x 4 tile, wave w the 4^3 brick at x offset 4 w,
-        // lane l the node (l % 4, l / 4 % 4, l / 16) of that brick (every axis a
-        // multiple of 16: no partial tiles)
-        const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
-        const int tix = L % p.tiles_x;
-        const int rem = L / p.tiles_x;
-        const int tiy = rem % p.tiles_y;
-        x = tix * 16 + w * 4 + (l & 3);
-        y = tiy * 4 + ((l >> 2) & 3);
-        z = (rem / p.tiles_y) * 4 + (l >> 4);
+        // brick layout: wave w of tile L updates the brick listed at [L][w] (the
+        // bricks that hold fluid, in storage order, so solid rock launches no
+        // wave), lane l the node (l % 4, l / 4 % 4, l / 16) of that brick; brick
+        // b is brick b % 64 of 16^3 block b / 64 (every axis a multiple of 16)
+        typedef const __attribute__((address_space(4))) int const_int;
+        const int l = threadIdx.x & 63;
+        const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        const int b = ((const_int *)p.tile_tag)[L * 4 + wave];
+        brick_none = b < 0;
+        const int bb = brick_none ? 0 : b;
+        const int blk = bb >> 6, bib = bb & 63;
         const Layout &ly = p.lay;
+        const int bz = blk / ly.nbxy, brem = blk - bz * ly.nbxy;
+        const int by = brem / ly.nbx, bx = brem - by * ly.nbx;
+        x = bx * 16 + (bib & 3) * 4 + (l & 3);
+        y = by * 16 + ((bib >> 2) & 3) * 4 + ((l >> 2) & 3);
+        z = bz * 16 + (bib >> 4) * 4 + (l >> 4);
         xo[0] = ly.x(x == 0 ? nx - 1 : x - 1), xo[1] = ly.x(x), xo[2] = ly.x(x + 1 == nx ? 0 : x + 1);
         yo[0] = ly.y(y == 0 ? ny - 1 : y - 1), yo[1] = ly.y(y), yo[2] = ly.y(y + 1 == ny ? 0 : y + 1);
         zo[0] = ly.z(z == 0 ? nz - 1 : z - 1), zo[1] = ly.z(z), zo[2] = ly.z(z + 1 == nz ? 0 : z + 1);
@@ -674,7 +681,7 @@ __global__ __launch_bounds__(256) void k_collide_stream(StepParams p) {
         // wave-uniform entry read through the constant address space (scalar load)
         typedef const __attribute__((address_space(4))) int const_int;
         const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-        const int tile_tag = ((const_int *)p.tile_tag)[L * 4 + wave];
+        const int tile_tag = BRICK ? (brick_none ? -1 : 0) : ((const_int *)p.tile_tag)[L * 4 + wave];
         if (tile_tag > 0) {
             tag = tile_tag;
             plain = true;
