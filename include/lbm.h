@@ -209,7 +209,12 @@ void lbm_destroy(lbm_lattice *lat);
  * shape); this exists for tuning and for that test.  The shape also decides whether a lattice
  * whose nx is a power of two in [64, 4096] uses row-form addressing (tx >= 64;
  * FP16 storage, or a tagged lattice with at least half of its nodes fluid; the
- * variant name then ends in "/rows").  EINVAL for other shapes. */
+ * variant name then ends in "/rows").  By default an FP16 lattice of one fluid
+ * model without walls whose nx is a power of two in [128, 4096] runs its even
+ * steps with two nodes per thread (variant "/pairs"; the same node update, so
+ * the populations agree with the one-node kernels up to where the compiler
+ * fuses a multiply-add differently, one FP16 rounding at most); an explicit
+ * shape selects the one-node kernels for every step.  EINVAL for other shapes. */
 lbm_status lbm_set_launch(lbm_lattice *lat, int tx, int ty);  /* EUNSUPPORTED on brick-layout lattices */
 
 /* ---------------------------------------------------------- initial state */
@@ -431,7 +436,9 @@ const char *lbm_last_error(void);
 
 /* Name of the kernel variant the handle selected: "D3Q<q>/<precision>/<model
  * set>/<uniform|tagged>", plus "/rows" when the step uses row-form addressing
- * (a wave's population rows start at wave-uniform addresses).  Owned by the
+ * (a wave's population rows start at wave-uniform addresses), "/pairs" when
+ * FP16 even steps update two nodes per thread (odd steps in row form), or
+ * "/bricks" for the brick storage layout.  Owned by the
  * handle; valid until the next lbm_set_launch or lbm_destroy. */
 const char *lbm_variant_name(const lbm_lattice *lat);
 

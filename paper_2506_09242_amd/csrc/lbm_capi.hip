@@ -59,6 +59,7 @@ struct lbm_lattice {
     int uniform_tag = LBM_TAG_BGK;
     int tx_log2 = 8;
     bool brick = false;             // brick storage layout (see Layout)
+    bool pair = false;              // FP16 even step with two nodes per lane (k_collide_pair_even)
     int tiles_x = 1, tiles_y = 1, n_tiles = 1;
     long long n_fluid = 0;
     bool failed = false;
@@ -222,12 +223,14 @@ StepParams step_params(const lbm_lattice *L) {
     const long long n_nodes = (long long)c.nx * c.ny * c.nz;
     const bool rows_pay = c.prec == LBM_F16S || (L->tagged && 2 * L->n_fluid >= n_nodes);
     p.row_log2 = -1;
-    if (rows_pay && !L->brick && L->tx_log2 >= 6 && c.nx >= 64 && c.nx <= (int)kBlockNodes &&
+    if (rows_pay && !L->brick && (L->pair || L->tx_log2 >= 6) && c.nx >= 64 && c.nx <= (int)kBlockNodes &&
         (c.nx & (c.nx - 1)) == 0) {
         int l = 0;
         while ((c.nx << l) < (int)kBlockNodes) ++l;
         p.row_log2 = l;
     }
+    p.pair = L->pair ? 1 : 0;
+    p.n_segs = L->pair ? (int)(n_nodes / 128) : 0;
     p.mask = L->d_mask;
     p.uniform_tag = L->uniform_tag;
     p.has_force = (c.force[0] != 0.0 || c.force[1] != 0.0 || c.force[2] != 0.0) ? 1 : 0;
@@ -256,7 +259,8 @@ void name_variant(lbm_lattice *L) {
     const lbm_config &c = L->cfg;
     snprintf(L->variant, sizeof L->variant, "D3Q%d/%s/%s/%s%s", c.q,
              c.prec == LBM_F64 ? "f64" : (c.prec == LBM_F32 ? "f32" : "f16s"), ms,
-             L->tagged ? "tagged" : "uniform", L->brick ? "/bricks" : (step_params(L).row_log2 >= 0 ? "/rows" : ""));
+             L->tagged ? "tagged" : "uniform",
+             L->brick ? "/bricks" : (L->pair ? "/pairs" : (step_params(L).row_log2 >= 0 ? "/rows" : "")));
 }
 
 AuxParams aux_params(const lbm_lattice *L) {
@@ -517,6 +521,10 @@ static lbm_status create_impl(const lbm_config *cfg, const uint8_t *tags_host, v
     L->tagged = tagged;
     L->uniform_tag = only;
     L->brick = brick;
+    // FP16 lattices of one model without walls whose rows tile the 4096-node
+    // blocks and hold whole 128-node segments: even steps with two nodes per lane
+    L->pair = cfg->prec == LBM_F16S && !tagged && (ms & MS_MLP) == 0 && cfg->nx >= 128 &&
+              cfg->nx <= (int)kBlockNodes && (cfg->nx & (cfg->nx - 1)) == 0;
     choose_tiles(L, default_txl(cfg->nx));
     name_variant(L);
 
@@ -679,6 +687,7 @@ extern "C" lbm_status lbm_set_launch(lbm_lattice *lat, int tx, int ty) {
     for (int k = 5; k <= 8; ++k)
         if (tx == (1 << k)) l = k;
     if (l < 0 || tx * ty != 256) return set_err(LBM_EINVAL, "tile must be tx in {32,64,128,256} with tx*ty = 256");
+    lat->pair = false;  // an explicit tile selects the one-node kernels
     choose_tiles(lat, l);
     name_variant(lat);
     if (lat->tagged) HIPCHK(lat, launch_tile_classify(step_params(lat), lat->d_tile_tag, lat->stream));

@@ -81,6 +81,8 @@ struct StepParams {
                               // bricks holding fluid / 4, rounded up
     int tiles_per_xcd;        // ceil(n_tiles / 8)
     int tx_log2;              // tile width = 1 << tx_log2, height = 256 >> tx_log2
+    int pair;                 // FP16 even step with two nodes per lane (k_collide_pair_even)
+    int n_segs;               // its 128-node row segments (nx ny nz / 128; a tile is four)
     int row_log2;             // log2(rows per 4096-node block) when whole rows tile the
                               // blocks and a tile is at least a wave wide, else -1
     int uniform_tag;          // model tag of every node (untagged variants)

@@ -915,6 +915,82 @@ __global__ __launch_bounds__(256) void k_collide_stream(StepParams p) {
     }
 }
 
+// ---- FP16 storage, two nodes per lane (even step)
+//
+// Lattices of one fluid model without walls (untagged), stored in FP16, whose
+// rows of 128..4096 nodes tile the 4096-node blocks.  Wave w of tile L updates
+// the 128-node row segment 4 L + w, lane l its nodes x0 = 2 l and x0 + 1 from
+// the segment start, reading and writing each population row with aligned
+// 4-byte accesses (a wave moves 256 contiguous bytes per row instead of 128).
+// The even step only: every access stays at the nodes themselves (an odd step
+// in this form, its x-shifted rows combined across lanes with DPP shifts, ran
+// slower than the one-node odd step at two waves per SIMD).  The node update is
+// the one-node code run twice; where the compiler shares a product between the
+// two nodes it may fuse one multiply-add fewer, so a rare population differs
+// from the one-node kernels' by one FP16 rounding.
+__device__ __forceinline__ float half_lo(uint32_t v) {
+    return (float)__builtin_bit_cast(_Float16, (unsigned short)(v & 0xffffu));
+}
+__device__ __forceinline__ float half_hi(uint32_t v) { return (float)__builtin_bit_cast(_Float16, (unsigned short)(v >> 16)); }
+__device__ __forceinline__ uint32_t half_bits(float v) { return (uint32_t)__builtin_bit_cast(unsigned short, (_Float16)v); }
+
+template <int Q, int MS>
+__global__ __launch_bounds__(256) void k_collide_pair_even(StepParams p) {
+    using C = float;
+    // tiles of four segments, dealt to the XCDs in contiguous runs (as k_collide_stream)
+    const int n_tiles = (p.n_segs + 3) >> 2;
+    const int per_xcd = (n_tiles + 7) >> 3;
+    const int wg = blockIdx.x;
+    const int L = (wg & 7) * per_xcd + (wg >> 3);
+    if (L >= n_tiles) return;  // uniform for the block
+    const int sg = L * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (sg >= p.n_segs) return;  // uniform for the wave (the last tile may be short)
+    const int lane = threadIdx.x & 63;
+    const int nx = p.nx, ny = p.ny;
+    const long long s0 = (long long)sg * 128;  // natural index of the segment's first node
+    const int nxl = __builtin_ctz((unsigned)nx);
+    const int xs = (int)(s0 & (nx - 1));
+    const int r = (int)(s0 >> nxl);            // row z ny + y
+    const int rl = p.row_log2;
+    // population 0 at x = 0 of the row, and the lane's byte offset in it
+    _Float16 *__restrict__ f = static_cast<_Float16 *>(p.pops);
+    const _Float16 *row =
+        f + (long long)(r >> rl) * (long long)(Q << kBlockLog2) + (long long)((r & ((1 << rl) - 1)) * nx);
+    const unsigned xb = (unsigned)(xs + 2 * lane) * 2u;
+    typedef __attribute__((address_space(1))) uint32_t gU32;
+    typedef __attribute__((address_space(1))) char gchar;
+    auto at = [&](int slot) -> gU32 * {
+        gchar *b = (gchar *)(row + slot_off(slot));
+        asm("" : "+s"(b));  // scalar base, lane offset added per access
+        return (gU32 *)(b + xb);
+    };
+    (void)ny;
+
+    // u[i]: h_i of both nodes (low half: x0, high half: x0 + 1)
+    uint32_t u[Q], o[Q];
+    sfor<Q>([&](auto I) { u[decltype(I)::value] = *at(decltype(I)::value); });
+    const int tag = p.uniform_tag;
+    sfor<2>([&](auto K) {
+        constexpr int k = decltype(K)::value;
+        C h[Q], hs[Q];
+        sfor<Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            h[i] = k == 0 ? half_lo(u[i]) : half_hi(u[i]);
+        });
+        collide_node<Q, C, MS, true>(h, tag, true, p, hs);
+        sfor<Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            if constexpr (k == 0) o[i] = half_bits(hs[i]);
+            else o[i] |= half_bits(hs[i]) << 16;
+        });
+    });
+    // h*_i to slot opp(i) of the nodes themselves
+    sfor<Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        *at(V<Q, i>::opp) = o[i];
+    });
+}
+
 // Neighbour mask of every node (see kMask*): wall bits, moving-wall flag and
 // the node's own fluid tag (0 for non-fluid nodes); tags and masks in storage
 // order (lay).
@@ -1131,6 +1207,14 @@ static hipError_t launch_step_par(const StepParams &p, int parity, hipStream_t s
     if constexpr (TG) {
         if (p.lay.brick) return launch_step_rows<Q, P, MS, TG, MODE, 2>(p, parity, s);
     }
+    if constexpr (P == 2 && !TG && (MS & MS_MLP) == 0 && MODE == MODE_STEP) {
+        // the even step of FP16 lattices of one model: two nodes per lane
+        if (p.pair && parity == 0) {
+            const int n_tiles = (p.n_segs + 3) / 4;
+            k_collide_pair_even<Q, MS><<<dim3(8 * ((n_tiles + 7) / 8)), dim3(256), 0, s>>>(p);
+            return hipGetLastError();
+        }
+    }
     constexpr bool kRows = P == 2 || TG;
     if constexpr (kRows) {
         if (p.row_log2 >= 0) return launch_step_rows<Q, P, MS, TG, MODE, 1>(p, parity, s);
@@ -1147,27 +1231,26 @@ static hipError_t launch_step_mode(const StepParams &p, int mode, int parity, hi
     }
 }
 
-template <int Q, int P, int MS>
-static hipError_t launch_step_geo(const StepParams &p, bool tagged, int mode, int parity, hipStream_t s) {
-    return tagged ? launch_step_mode<Q, P, MS, true>(p, mode, parity, s)
-                  : launch_step_mode<Q, P, MS, false>(p, mode, parity, s);
+template <int Q, int P, bool TG>
+static hipError_t launch_step_ms(const StepParams &p, int ms, int mode, int parity, hipStream_t s) {
+    switch (ms) {
+        case MS_BGK: return launch_step_mode<Q, P, MS_BGK, TG>(p, mode, parity, s);
+        case MS_TRT: return launch_step_mode<Q, P, MS_TRT, TG>(p, mode, parity, s);
+        case MS_BGK | MS_SMAG: return launch_step_mode<Q, P, MS_BGK | MS_SMAG, TG>(p, mode, parity, s);
+        case MS_BGK | MS_SMAG | MS_MLP: return launch_step_mode<Q, P, MS_BGK | MS_SMAG | MS_MLP, TG>(p, mode, parity, s);
+        case MS_REG: return launch_step_mode<Q, P, MS_REG, TG>(p, mode, parity, s);
+        case MS_TRT | MS_OPEN: return launch_step_mode<Q, P, MS_TRT | MS_OPEN, TG>(p, mode, parity, s);
+        case MS_RR: return launch_step_mode<Q, P, MS_RR, TG>(p, mode, parity, s);
+        case kAllModels: return launch_step_mode<Q, P, kAllModels, TG>(p, mode, parity, s);
+        case MS_STREAM: return launch_step_mode<Q, P, MS_STREAM, TG>(p, mode, parity, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 template <int Q, int P>
 hipError_t launch_step(const StepParams &p, int ms, bool tagged, int mode, int parity, hipStream_t s) {
-    switch (ms) {
-        case MS_BGK: return launch_step_geo<Q, P, MS_BGK>(p, tagged, mode, parity, s);
-        case MS_TRT: return launch_step_geo<Q, P, MS_TRT>(p, tagged, mode, parity, s);
-        case MS_BGK | MS_SMAG: return launch_step_geo<Q, P, MS_BGK | MS_SMAG>(p, tagged, mode, parity, s);
-        case MS_BGK | MS_SMAG | MS_MLP:
-            return launch_step_geo<Q, P, MS_BGK | MS_SMAG | MS_MLP>(p, tagged, mode, parity, s);
-        case MS_REG: return launch_step_geo<Q, P, MS_REG>(p, tagged, mode, parity, s);
-        case MS_TRT | MS_OPEN: return launch_step_geo<Q, P, MS_TRT | MS_OPEN>(p, tagged, mode, parity, s);
-        case MS_RR: return launch_step_geo<Q, P, MS_RR>(p, tagged, mode, parity, s);
-        case kAllModels: return launch_step_geo<Q, P, kAllModels>(p, tagged, mode, parity, s);
-        case MS_STREAM: return launch_step_geo<Q, P, MS_STREAM>(p, tagged, mode, parity, s);
-        default: return hipErrorInvalidValue;
-    }
+    return tagged ? launch_step_ms<Q, P, true>(p, ms, mode, parity, s)
+                  : launch_step_ms<Q, P, false>(p, ms, mode, parity, s);
 }
 
 template <int Q>

@@ -260,9 +260,25 @@ def test_launch_shape_is_bitwise_irrelevant(prec):
 F16S, F32, F64 = lbm.LBM_F16S, lbm.LBM_F32, lbm.LBM_F64
 
 
+def _within_f16_rounding(a, b, q, rho0, n_steps):
+    """Two FP16-storage runs that differ only where the compiler fused one
+    multiply-add differently: few populations differ, each by at most about
+    one FP16 rounding of its shifted value h = f - w rho0 per step taken."""
+    w = np.array([lbm.lbm_velocity(q, i)[1] for i in range(q)])
+    # populations first (read_populations) or last (read_cells)
+    w = w.reshape((1, q) if a.ndim == 2 else (q, 1, 1, 1))
+    h = np.abs(b - w * rho0)
+    d = np.abs(a - b)
+    frac = np.count_nonzero(d) / d.size
+    bound = n_steps * 2.0 ** -10 * h.max()
+    _print("f16 two-node vs one-node: differing fraction", frac, "max diff", d.max(), "bound", bound)
+    return frac < 1e-3 and d.max() <= bound
+
+
 @pytest.mark.parametrize("prec,q,nx,ny,nz,kind", [
     (F16S, 19, 64, 21, 9, "walls"), (F16S, 27, 128, 10, 7, "walls"), (F16S, 19, 4096, 3, 2, "walls"),
-    (F16S, 19, 64, 5, 11, "periodic"), (F16S, 27, 128, 9, 4, "periodic"), (F16S, 19, 256, 6, 5, "cavity"),
+    (F16S, 19, 64, 5, 11, "periodic"), (F16S, 27, 128, 9, 4, "periodic"), (F16S, 19, 256, 5, 3, "periodic"),
+    (F16S, 19, 128, 5, 3, "periodic"), (F16S, 19, 256, 6, 5, "cavity"),
     (F32, 19, 64, 21, 9, "walls"), (F32, 27, 128, 10, 7, "walls"), (F32, 19, 256, 12, 10, "cavity"),
     (F64, 19, 64, 21, 9, "walls"), (F64, 27, 256, 12, 10, "cavity"), (F32, 19, 64, 21, 9, "sparse"),
     (F64, 19, 64, 6, 8, "open"), (F16S, 27, 64, 6, 8, "open"),
@@ -292,9 +308,13 @@ def test_row_form_matches_node_form(prec, q, nx, ny, nz, kind):
         kw = dict(tau=0.6, wall_velocity=[(0.1, 0, 0)])
     rho, u = inputs.random_fields(nx, ny, nz, seed=7)
     outs, sers, names = [], [], []
-    for tx in (32, 64, 128, 256):
+    # explicit tiles (one node per lane), then the default launch, which for
+    # FP16 lattices of one model without walls and power-of-two rows of at
+    # least 128 nodes runs two nodes per lane
+    for tx in (32, 64, 128, 256, None):
         L = lbm.Lattice(tags, q=q, prec=prec, **kw)
-        L.set_launch(tx, 256 // tx)
+        if tx is not None:
+            L.set_launch(tx, 256 // tx)
         names.append(L.variant)
         L.init_equilibrium(rho, u)
         sers.append(L.step_reduce(9, 3))
@@ -304,9 +324,15 @@ def test_row_form_matches_node_form(prec, q, nx, ny, nz, kind):
     _print(prec, q, nx, ny, nz, kind, names)
     fluid = int(((tags >= 1) & (tags <= 10)).sum())
     rows = prec == F16S or 2 * fluid >= tags.size
-    assert not names[0].endswith("/rows") and all(n.endswith("/rows") == rows for n in names[1:])
-    for f, ser in zip(outs[1:], sers[1:]):
-        assert np.array_equal(f, outs[0])
+    assert not names[0].endswith("/rows") and all(n.endswith("/rows") == rows for n in names[1:4])
+    pairs = prec == F16S and kind == "periodic" and nx >= 128
+    assert names[4].endswith("/pairs") == pairs, names[4]
+    for k, (f, ser) in enumerate(zip(outs[1:], sers[1:])):
+        if k == 3 and pairs:
+            # the two-node even step: one FP16 rounding apart at most, rarely
+            assert _within_f16_rounding(f, outs[0], q, 1.0, 13)
+        else:
+            assert np.array_equal(f, outs[0])
         # reductions: the per-tile partials follow the tile shape, so the FP64
         # sums differ in summation order only
         for a, b in zip(ser, sers[0]):
@@ -318,9 +344,11 @@ def test_row_form_matches_node_form(prec, q, nx, ny, nz, kind):
 
 def test_row_form_full_size_tgv512_f16():
     """The 512^3 D3Q27 Taylor-Green lattice in FP16 storage (3.6e9 population
-    elements, past 2^31): row form (default tiles) and node form (32-wide tiles)
-    give bitwise-equal populations after an even and an odd step, on sampled
-    nodes that include the periodic faces and the last block of the array."""
+    elements, past 2^31): the row form (256-wide tiles) and the node form
+    (32-wide tiles) give bitwise-equal populations after an even and an odd
+    step, and the default launch (its even step with two nodes per lane) the
+    same up to a rare FP16 rounding, on sampled nodes that include the periodic
+    faces and the last block of the array."""
     tags, kw, rho, u, _ = _bench_workload("tgv512_d3q27_smag")
     nz, ny, nx = tags.shape
     rng = np.random.default_rng(11)
@@ -328,17 +356,19 @@ def test_row_form_full_size_tgv512_f16():
     tail = list(range(nx * ny * nz - 5000, nx * ny * nz))
     cells = np.unique(np.concatenate([faces, tail, rng.choice(nx * ny * nz, 20000, replace=False)]))
     outs, names = [], []
-    for tx in (256, 32):
+    for tx in (None, 256, 32):
         L = lbm.Lattice(tags, prec=lbm.LBM_F16S, **kw)
-        L.set_launch(tx, 256 // tx)
+        if tx is not None:
+            L.set_launch(tx, 256 // tx)
         names.append(L.variant)
         L.init_equilibrium(rho, u)
         L.step(2)
         outs.append(L.read_cells(cells))
         L.close()
     _print("tgv512 f16", names, cells.size)
-    assert names[0].endswith("/rows") and not names[1].endswith("/rows")
-    assert np.array_equal(outs[0], outs[1])
+    assert names[0].endswith("/pairs") and names[1].endswith("/rows") and not names[2].endswith("/rows")
+    assert np.array_equal(outs[1], outs[2])
+    assert _within_f16_rounding(outs[0], outs[2], 27, kw.get("rho0", 1.0), 2)
 
 def _box_cavity(nx, ny, nz):
     """Walls on all six faces, a moving lid (tag 16) on the top plane."""
