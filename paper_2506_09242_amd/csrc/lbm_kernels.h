@@ -946,7 +946,7 @@ __global__ __launch_bounds__(256) void k_collide_pair_even(StepParams p) {
     const int sg = L * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (sg >= p.n_segs) return;  // uniform for the wave (the last tile may be short)
     const int lane = threadIdx.x & 63;
-    const int nx = p.nx, ny = p.ny;
+    const int nx = p.nx;
     const long long s0 = (long long)sg * 128;  // natural index of the segment's first node
     const int nxl = __builtin_ctz((unsigned)nx);
     const int xs = (int)(s0 & (nx - 1));
@@ -964,7 +964,6 @@ __global__ __launch_bounds__(256) void k_collide_pair_even(StepParams p) {
         asm("" : "+s"(b));  // scalar base, lane offset added per access
         return (gU32 *)(b + xb);
     };
-    (void)ny;
 
     // u[i]: h_i of both nodes (low half: x0, high half: x0 + 1)
     uint32_t u[Q], o[Q];
