@@ -521,6 +521,40 @@ def _bench_workload(name):
     return bench.build_workload(name)
 
 
+def test_full_size_tgv512_sampled_cells():
+    """The headline workload at its full size and launch configuration (512^3
+    D3Q27 BGK+Smagorinsky Taylor-Green: the uniform kernels; in FP16 the
+    two-node even step) from the Taylor-Green state with random perturbations,
+    3 steps (an odd count: even and odd launches), in every precision: sampled
+    nodes (the periodic faces, the last storage block, random nodes) match the
+    oracle's populations (FP64 to 1e-12 relative; FP32 storage within 1e-6;
+    FP16 storage within 3 roundings of h)."""
+    tags, kw, rho, u, _ = _bench_workload("tgv512_d3q27_smag")
+    nz, ny, nx = tags.shape
+    r2, u2 = inputs.random_fields(nx, ny, nz, seed=79, du=0.005, drho=0.002)
+    rho, u = rho + (r2 - 1.0), u + u2
+    o = oracle.Oracle(nx, ny, nz, tags=tags, **kw)
+    o.init_equilibrium(rho, u)
+    o.run(3)
+    rng = np.random.default_rng(12)
+    faces = [((z * ny + y) * nx + x) for z in (0, nz - 1) for y in (0, 255, ny - 1) for x in range(nx)]
+    tail = list(range(nx * ny * nz - 4096, nx * ny * nz))
+    cells = np.unique(np.concatenate([faces, tail, rng.choice(nx * ny * nz, 20000, replace=False)]))
+    ref = o.f.reshape(kw["q"], -1)[:, cells].T
+    del o
+    for prec, bound in ((lbm.LBM_F64, TOL), (lbm.LBM_F32, 1e-6), (lbm.LBM_F16S, 3 * 2.0**-11)):
+        L = lbm.Lattice(tags, prec=prec, **kw)
+        L.init_equilibrium(rho, u)
+        L.step(3)
+        g = L.read_cells(cells)
+        name = L.variant
+        L.close()
+        err = float(np.abs(g / ref - 1.0).max())
+        _print("full tgv512", name, cells.size, err)
+        assert err <= bound
+    assert name.endswith("/pairs")
+
+
 def test_full_size_porous_sampled_cells():
     """The porous-rock workload at its full size and launch configuration (400^3
     D3Q19 TRT with body force: brick layout, waves only for the bricks that
