@@ -555,14 +555,17 @@ def test_full_size_tgv512_sampled_cells():
     assert name.endswith("/pairs")
 
 
-def test_full_size_porous_sampled_cells():
-    """The porous-rock workload at its full size and launch configuration (400^3
-    D3Q19 TRT with body force: brick layout, waves only for the bricks that
-    hold fluid) from a random near-rest state, 11 steps, in every precision:
-    sampled fluid nodes (random ones and nodes next to the rock) match the
-    oracle's populations (FP64 to 1e-12 relative; FP32 storage within 1e-5;
-    FP16 storage within 11 roundings of h, as for the cavity)."""
-    tags, kw, _, _, _ = _bench_workload("porous400_d3q19_trt")
+@pytest.mark.parametrize("workload", ["porous400_d3q19_trt", "porous480_open_d3q19_trt"])
+def test_full_size_porous_sampled_cells(workload):
+    """The porous-rock workloads at their full size and launch configuration
+    (400^3 D3Q19 TRT with a body force, and the same rock between 40-plane
+    buffers with pressure boundaries, 480 x 400 x 400: brick layout, waves
+    only for the bricks that hold fluid) from a random near-rest state, 11
+    steps, in every precision: sampled fluid nodes (random ones, nodes next to
+    the rock and, with buffers, the boundary planes) match the oracle's
+    populations (FP64 to 1e-12 relative; FP32 storage within 1e-5; FP16
+    storage within 11 roundings of h, as for the cavity)."""
+    tags, kw, _, _, _ = _bench_workload(workload)
     nz, ny, nx = tags.shape
     rho, u = inputs.random_fields(nx, ny, nz, seed=78, du=0.01, drho=0.005)
     o = oracle.Oracle(nx, ny, nz, tags=tags, **kw)
@@ -574,8 +577,12 @@ def test_full_size_porous_sampled_cells():
     near = fl3 & ~(np.roll(fl3, 1, 0) & np.roll(fl3, -1, 0) & np.roll(fl3, 1, 1) & np.roll(fl3, -1, 1)
                    & np.roll(fl3, 1, 2) & np.roll(fl3, -1, 2))
     rng = np.random.default_rng(6)
-    cells = np.unique(np.concatenate([rng.choice(fl, 20000, replace=False),
-                                      rng.choice(np.flatnonzero(near.reshape(-1)), 5000, replace=False)]))
+    picks = [rng.choice(fl, 20000, replace=False), rng.choice(np.flatnonzero(near.reshape(-1)), 5000, replace=False)]
+    if workload == "porous480_open_d3q19_trt":
+        # the inlet and outlet planes and their neighbours
+        for x in (0, 1, nx - 2, nx - 1):
+            picks.append(rng.choice(np.arange(ny * nz) * nx + x, 1000, replace=False))
+    cells = np.unique(np.concatenate(picks))
     ref = o.f.reshape(kw["q"], -1)[:, cells].T
     del o
     for prec, bound in ((lbm.LBM_F64, TOL), (lbm.LBM_F32, 1e-5), (lbm.LBM_F16S, 11 * 2.0**-11)):
